@@ -1,0 +1,98 @@
+"""Pins of the oracle's default observation (Sec. 3.2: objects in the agent's
+frame, road graph sub-sampled by distance)."""
+import json
+import math
+import os
+
+import numpy as np
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _objs(x, y, yaw, vx, vy, valid=None):
+    n = len(x)
+    return {"x": np.asarray(x, float), "y": np.asarray(y, float), "yaw": np.asarray(yaw, float),
+            "vx": np.asarray(vx, float), "vy": np.asarray(vy, float), "length": np.full(n, 4.5),
+            "width": np.full(n, 2.0), "valid": np.ones(n, np.uint8) if valid is None else np.asarray(valid, np.uint8)}
+
+
+def _rg(xy, valid=None):
+    xy = np.asarray(xy, float)
+    P = xy.shape[0]
+    ang = np.arange(P) * 0.37
+    return {"x": xy[:, 0], "y": xy[:, 1], "dir_x": np.cos(ang), "dir_y": np.sin(ang),
+            "type": (np.arange(P) % 2).astype(np.int8),
+            "valid": np.ones(P, np.uint8) if valid is None else np.asarray(valid, np.uint8)}
+
+
+def test_exact_tie_fixture():
+    g = json.load(open(os.path.join(GOLDEN, "topk_exact_ties.json")))
+    objs = _objs([g["ego"]["x"]], [g["ego"]["y"]], [g["ego"]["yaw"]], [0.0], [0.0])
+    pts = np.asarray(g["points"], float)
+    idx, rf, _ = oracle.observe(np.array([0, 1], np.int32), np.array([0, len(pts)], np.int32), objs, _rg(pts),
+                                np.array([[0]], np.int32), g["k"], 1)
+    assert idx[0, 0].tolist() == g["expected_idx"]
+    d2 = rf[0, 0, :, 0] ** 2 + rf[0, 0, :, 1] ** 2
+    np.testing.assert_allclose(d2, g["expected_d2"], atol=1e-12)
+
+
+def test_topk_equals_stable_sort_and_pads():
+    rng = np.random.default_rng(30)
+    P, k = 700, 64
+    pts = rng.uniform(-60, 60, (P, 2)).round(1)   # 0.1 m grid: many exact ties
+    valid = (rng.random(P) > 0.1).astype(np.uint8)
+    objs = _objs([3.0, -7.2], [1.5, 4.4], [0.4, -2.0], [1.0, 0.0], [0.0, 2.0])
+    idx, rf, _ = oracle.observe(np.array([0, 2], np.int32), np.array([0, P], np.int32), objs,
+                                _rg(pts, valid), np.array([[0, 1]], np.int32), k, 2)
+    for e in range(2):
+        ex, ey = np.float32(objs["x"][e]), np.float32(objs["y"][e])
+        dx = pts[:, 0].astype(np.float32) - ex
+        dy = pts[:, 1].astype(np.float32) - ey
+        key = (dx * dx + dy * dy).astype(np.float32)
+        cand = np.flatnonzero(valid)
+        order = cand[np.argsort(key[cand], kind="stable")]
+        assert idx[0, e].tolist() == order[:k].tolist()
+    # more slots than valid points: padded with -1 and zero features
+    idx2, rf2, _ = oracle.observe(np.array([0, 2], np.int32), np.array([0, 5], np.int32), objs,
+                                  _rg(pts[:5], valid[:5]), np.array([[1, 0]], np.int32), 8, 2)
+    nv = int(valid[:5].sum())
+    assert (idx2[0, 0, nv:] == -1).all() and (idx2[0, 0, :nv] >= 0).all()
+    assert (rf2[0, 0, nv:] == 0).all()
+
+
+def test_frame_transform_properties():
+    rng = np.random.default_rng(31)
+    n = 9
+    objs = _objs(rng.uniform(-50, 50, n), rng.uniform(-50, 50, n), rng.uniform(-3, 3, n),
+                 rng.uniform(-9, 9, n), rng.uniform(-9, 9, n), valid=[1] * 8 + [0])
+    pts = rng.uniform(-50, 50, (40, 2))
+    rg = _rg(pts)
+    ego = np.array([[0, 4, 8]], np.int32)
+    idx, rf, of = oracle.observe(np.array([0, n], np.int32), np.array([0, 40], np.int32), objs, rg, ego, 40, 10)
+    for e, g in enumerate(ego[0][:2]):
+        f = of[0, e]
+        # the ego maps to the origin, heading 0, speed along +x
+        np.testing.assert_allclose(f[g, :3], 0.0, atol=1e-12)
+        np.testing.assert_allclose(f[g, 3], math.hypot(objs["vx"][g], objs["vy"][g]) *
+                                   math.cos(math.atan2(objs["vy"][g], objs["vx"][g]) - objs["yaw"][g]), atol=1e-12)
+        # distances and speeds are preserved; rotating back recovers the world
+        c, s = math.cos(objs["yaw"][g]), math.sin(objs["yaw"][g])
+        wx = c * f[:8, 0] - s * f[:8, 1] + objs["x"][g]
+        wy = s * f[:8, 0] + c * f[:8, 1] + objs["y"][g]
+        np.testing.assert_allclose(wx, objs["x"][:8], atol=1e-10)
+        np.testing.assert_allclose(wy, objs["y"][:8], atol=1e-10)
+        np.testing.assert_allclose(np.hypot(f[:8, 3], f[:8, 4]), np.hypot(objs["vx"][:8], objs["vy"][:8]), atol=1e-10)
+        yaw_rel = f[:8, 2]
+        assert (yaw_rel >= -math.pi).all() and (yaw_rel < math.pi).all()
+        np.testing.assert_allclose(np.cos(yaw_rel), np.cos(objs["yaw"][:8] - objs["yaw"][g]), atol=1e-12)
+        assert (f[8] == 0).all() and (f[9] == 0).all()    # invalid object and padded slot
+        # road features: ascending distances, unit directions preserved
+        d = np.hypot(rf[0, e, :, 0], rf[0, e, :, 1])
+        assert (np.diff(d) >= -1e-6).all()
+        np.testing.assert_allclose(d, np.hypot(pts[idx[0, e], 0] - objs["x"][g], pts[idx[0, e], 1] - objs["y"][g]),
+                                   atol=1e-10)
+        np.testing.assert_allclose(np.hypot(rf[0, e, :, 2], rf[0, e, :, 3]), 1.0, atol=1e-12)
+    # invalid ego: everything padded
+    assert (idx[0, 2] == -1).all() and (rf[0, 2] == 0).all() and (of[0, 2] == 0).all()

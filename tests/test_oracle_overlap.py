@@ -1,0 +1,173 @@
+"""Pins of the oracle's collision metric (Sec. 3.4, Collision: 2D top-down
+box overlap) against polygon clipping, per-corner projections, an
+axis-aligned closed form and geometric invariances."""
+import math
+
+import numpy as np
+
+import oracle
+
+
+def corners(x, y, yaw, length, width):
+    c, s = math.cos(yaw), math.sin(yaw)
+    hl, hw = length / 2, width / 2
+    return [(x + sl * hl * c - sw * hw * s, y + sl * hl * s + sw * hw * c)
+            for sl, sw in ((1, 1), (-1, 1), (-1, -1), (1, -1))]  # counter-clockwise
+
+
+def clip_area(subject, clipper):
+    """Sutherland-Hodgman clipping of convex CCW polygons; returns the area of
+    the intersection."""
+    def inside(p, a, b):
+        return (b[0] - a[0]) * (p[1] - a[1]) - (b[1] - a[1]) * (p[0] - a[0]) > 0
+
+    def cross_point(p, q, a, b):
+        x1, y1, x2, y2 = p[0], p[1], q[0], q[1]
+        x3, y3, x4, y4 = a[0], a[1], b[0], b[1]
+        den = (x1 - x2) * (y3 - y4) - (y1 - y2) * (x3 - x4)
+        t = ((x1 - x3) * (y3 - y4) - (y1 - y3) * (x3 - x4)) / den
+        return (x1 + t * (x2 - x1), y1 + t * (y2 - y1))
+
+    out = list(subject)
+    for i in range(len(clipper)):
+        a, b = clipper[i], clipper[(i + 1) % len(clipper)]
+        inp, out = out, []
+        if not inp:
+            break
+        prev = inp[-1]
+        for cur in inp:
+            if inside(cur, a, b):
+                if not inside(prev, a, b):
+                    out.append(cross_point(prev, cur, a, b))
+                out.append(cur)
+            elif inside(prev, a, b):
+                out.append(cross_point(prev, cur, a, b))
+            prev = cur
+    if len(out) < 3:
+        return 0.0
+    return 0.5 * sum(out[i][0] * out[(i + 1) % len(out)][1] - out[(i + 1) % len(out)][0] * out[i][1]
+                     for i in range(len(out)))
+
+
+def projection_margin(A, B):
+    """Smallest translation that separates the two corner sets' projections,
+    over the four face normals (computed from the corner polygons, not from
+    box radii); negative when the projections are already apart."""
+    best = None
+    for P in (A, B):
+        for i in (0, 1):
+            ex, ey = P[i + 1][0] - P[i][0], P[i + 1][1] - P[i][1]
+            nrm = math.hypot(ex, ey)
+            ax, ay = -ey / nrm, ex / nrm
+            pa = [px * ax + py * ay for px, py in A]
+            pb = [px * ax + py * ay for px, py in B]
+            ov = min(max(pa) - min(pb), max(pb) - min(pa))
+            best = ov if best is None else min(best, ov)
+    return best
+
+
+def _random_box(rng, spread):
+    return (rng.uniform(-spread, spread), rng.uniform(-spread, spread), rng.uniform(-math.pi, math.pi),
+            rng.uniform(1.0, 6.0), rng.uniform(0.5, 3.0))
+
+
+def test_margin_sign_matches_polygon_clipping():
+    rng = np.random.default_rng(10)
+    checked = 0
+    for _ in range(3000):
+        a, b = _random_box(rng, 4.0), _random_box(rng, 4.0)
+        m = oracle.sat_margin(a, b)
+        if abs(m) < 1e-6:
+            continue
+        area = clip_area(corners(*a), corners(*b))
+        assert (m > 0) == (area > 1e-12), (a, b, m, area)
+        checked += 1
+    assert checked > 2500
+
+
+def test_near_touching_pairs():
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        a = _random_box(rng, 0.0)
+        yaw_b = rng.uniform(-math.pi, math.pi)
+        b0 = (0.0, 0.0, yaw_b, rng.uniform(1, 6), rng.uniform(0.5, 3))
+        # slide b along a random direction until the clipping area vanishes
+        d = rng.uniform(-math.pi, math.pi)
+        lo, hi = 0.0, 20.0
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            bb = (mid * math.cos(d), mid * math.sin(d)) + b0[2:]
+            if clip_area(corners(*a), corners(*bb)) > 0:
+                lo = mid
+            else:
+                hi = mid
+        for off, sign in ((-1e-3, 1), (1e-3, -1)):
+            r = 0.5 * (lo + hi) + off
+            bb = (r * math.cos(d), r * math.sin(d)) + b0[2:]
+            m = oracle.sat_margin(a, bb)
+            assert (m > 0) == (sign > 0), (a, bb, m)
+
+
+def test_margin_equals_corner_projection_margin():
+    rng = np.random.default_rng(12)
+    for _ in range(2000):
+        a, b = _random_box(rng, 6.0), _random_box(rng, 6.0)
+        assert abs(oracle.sat_margin(a, b) - projection_margin(corners(*a), corners(*b))) < 1e-9
+
+
+def test_axis_aligned_closed_form():
+    rng = np.random.default_rng(13)
+    for _ in range(500):
+        la, wa, lb, wb = rng.uniform(1, 6, 4)
+        dx, dy = rng.uniform(-8, 8, 2)
+        for yb in (0.0, math.pi):   # a 180-degree flip is the same box
+            m = oracle.sat_margin((1.0, 2.0, 0.0, la, wa), (1.0 + dx, 2.0 + dy, yb, lb, wb))
+            expect = min((la + lb) / 2 - abs(dx), (wa + wb) / 2 - abs(dy))
+            assert abs(m - expect) < 1e-12
+
+
+def test_symmetry_rigid_motion_and_permutation():
+    rng = np.random.default_rng(14)
+    n = 12
+    st = {"x": rng.uniform(-6, 6, n), "y": rng.uniform(-6, 6, n), "yaw": rng.uniform(-3, 3, n),
+          "vx": np.zeros(n), "vy": np.zeros(n), "length": rng.uniform(3, 6, n),
+          "width": rng.uniform(1.5, 2.5, n), "valid": np.ones(n, np.uint8)}
+    st["valid"][3] = 0
+    off = np.array([0, n], np.int32)
+    col, mm, (M,) = oracle.overlap(off, st, matrix=True)
+    np.testing.assert_allclose(M, M.T, atol=1e-12)
+    assert (np.diag(M) == oracle.NO_VALUE).all()
+    assert (M[3] == oracle.NO_VALUE).all() and (M[:, 3] == oracle.NO_VALUE).all()
+    assert col[3] == 0 and mm[3] == oracle.NO_VALUE
+    np.testing.assert_array_equal(col, (mm > 0).astype(np.uint8))
+    assert 0 < col.sum() < n  # the scene has both outcomes
+    # rigid motion
+    phi, tx, ty = -1.1, 30.0, 7.0
+    c, s = math.cos(phi), math.sin(phi)
+    r = dict(st)
+    r["x"], r["y"] = c * st["x"] - s * st["y"] + tx, s * st["x"] + c * st["y"] + ty
+    r["yaw"] = st["yaw"] + phi
+    _, _, (Mr,) = oracle.overlap(off, r, matrix=True)
+    np.testing.assert_allclose(Mr, M, atol=1e-9)
+    # permutation
+    perm = rng.permutation(n)
+    p = {k: v[perm] for k, v in st.items()}
+    _, _, (Mp,) = oracle.overlap(off, p, matrix=True)
+    np.testing.assert_allclose(Mp, M[np.ix_(perm, perm)], atol=1e-12)
+
+
+def test_ragged_batch_blocks_are_independent():
+    rng = np.random.default_rng(15)
+    counts = [3, 1, 5]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    n = off[-1]
+    st = {"x": rng.uniform(-3, 3, n), "y": rng.uniform(-3, 3, n), "yaw": rng.uniform(-3, 3, n),
+          "vx": np.zeros(n), "vy": np.zeros(n), "length": np.full(n, 4.0), "width": np.full(n, 2.0),
+          "valid": np.ones(n, np.uint8)}
+    col, mm, blocks = oracle.overlap(off, st, matrix=True)
+    for s, N in enumerate(counts):
+        sub = {k: v[off[s]:off[s + 1]] for k, v in st.items()}
+        c2, m2, (B,) = oracle.overlap(np.array([0, N], np.int32), sub, matrix=True)
+        np.testing.assert_array_equal(B, blocks[s])
+        np.testing.assert_array_equal(m2, mm[off[s]:off[s + 1]])
+    assert mm[3] == oracle.NO_VALUE  # single-object scenario: no partner

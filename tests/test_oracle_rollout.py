@@ -1,0 +1,162 @@
+"""Pins of the oracle's rollout (Sec. 5.1 Rollout, Sec. 4.1 step) and of its
+hand-written reverse-mode gradient (differentiable simulation, Sec. 1 and
+Sec. 6) against expert replay, finite differences and a closed form."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_08710_amd import synth
+
+DT = 0.1
+
+
+def _f64(d):
+    return {k: (v.astype(np.float64) if v.dtype == np.float32 else v) for k, v in d.items()}
+
+
+def test_expert_actions_replay_bicycle_logs_exactly():
+    # Logs produced by the bicycle model itself are reproduced by the expert
+    # (inverse dynamics) actions: log divergence stays at rounding level.
+    sc = synth.make_scene(0, steps=20)
+    n, T = sc.total_objects, sc.steps
+    init = _f64(sc.state_at(synth.T0))
+    rng = np.random.default_rng(40)
+    a = rng.uniform(-1, 3, (T, n))
+    k = rng.uniform(-0.1, 0.1, (T, n))
+    ctrl = np.ones(n, np.uint8)
+    logs = [init]
+    for t in range(T):
+        logs.append(oracle.bicycle_forward(logs[-1], a[t], k[t], ctrl, logs[-1], DT))
+    log_seq = {f: np.stack([l[f] for l in logs]) for f in init}
+    ea = np.zeros((T, n))
+    ek = np.zeros((T, n))
+    for t in range(T):
+        ea[t], ek[t], _ = oracle.bicycle_inverse(logs[t], logs[t + 1], DT)
+    out = oracle.rollout(sc.obj_off, sc.rg_off, init, ea, ek, ctrl, log_seq, _f64(sc.rg), T, DT)
+    assert out["log_div"].max() < 1e-9
+    np.testing.assert_allclose(out["traj"]["x"], log_seq["x"][1:], atol=1e-9)
+
+
+def test_rollout_equals_loop_of_steps_and_metrics():
+    sc = synth.make_scene(0, object_box=15, on_road_frac=0.5, invalid_frac=0.15)
+    n, T = sc.total_objects, sc.steps
+    init, lw, rg = _f64(sc.state_at(synth.T0)), _f64(sc.log_window()), _f64(sc.rg)
+    ctrl = sc.controlled.copy()
+    ctrl[::3] = 0
+    out = oracle.rollout(sc.obj_off, sc.rg_off, init, sc.accel, sc.curvature, ctrl, lw, rg, T, DT)
+    s = init
+    for t in range(1, T + 1):
+        lg = {f: lw[f][t] for f in lw}
+        s = oracle.bicycle_forward(s, sc.accel[t - 1].astype(float), sc.curvature[t - 1].astype(float), ctrl, lg, DT)
+        for f in s:
+            np.testing.assert_array_equal(out["traj"][f][t - 1], s[f])
+        col, mm, _ = oracle.overlap(sc.obj_off, s)
+        r = oracle.offroad(sc.obj_off, sc.rg_off, s, rg)
+        np.testing.assert_array_equal(out["collision"][t - 1], col)
+        np.testing.assert_array_equal(out["overlap_margin"][t - 1], mm)
+        np.testing.assert_array_equal(out["offroad"][t - 1], r["offroad"])
+        np.testing.assert_array_equal(out["log_div"][t - 1], oracle.log_divergence(s, lg))
+    assert out["collision"].any() and not out["collision"].all()
+
+
+def _grad_scene(seed_scen=3):
+    sc = synth.make_scene(3, scenarios=2, objects=(12, 12), rg_points=(240, 240), steps=12,
+                          object_box=12)
+    init, lw = _f64(sc.state_at(synth.T0)), _f64(sc.log_window())
+    return sc, init, lw
+
+
+def test_gradient_matches_central_differences():
+    sc, init, lw = _grad_scene()
+    T, n = sc.steps, sc.total_objects
+    a, k = sc.accel.astype(float), sc.curvature.astype(float)
+    dl = np.array([1.0, 0.5])
+    ga, gk, loss = oracle.rollout_grad(sc.obj_off, init, a, k, sc.controlled, lw, T, DT, dl)
+    assert loss[0] > 0
+    h = 1e-6
+    rng = np.random.default_rng(41)
+    ctrl_ids = np.flatnonzero(sc.controlled)
+    checked = 0
+    for _ in range(60):
+        t, i = rng.integers(0, T), rng.choice(ctrl_ids)
+        for arr, g in ((a, ga), (k, gk)):
+            old = arr[t, i]
+            arr[t, i] = old + h
+            lp = oracle.rollout_loss(sc.obj_off, init, a, k, sc.controlled, lw, T, DT) @ dl
+            arr[t, i] = old - h
+            lm = oracle.rollout_loss(sc.obj_off, init, a, k, sc.controlled, lw, T, DT) @ dl
+            arr[t, i] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[t, i]) <= 1e-5 * max(1.0, abs(fd)), (t, i, fd, g[t, i])
+            checked += 1
+    assert checked == 120
+    # uncontrolled objects never receive a gradient
+    assert (ga[:, sc.controlled == 0] == 0).all() and (gk[:, sc.controlled == 0] == 0).all()
+
+
+def test_soft_overlap_gradient_is_exercised():
+    # Put two controlled boxes nearly on top of each other so the sigmoid term
+    # dominates, and check its gradient by finite differences too.
+    n, T = 2, 3
+    yaw = 0.1
+    wx, wy = -math.sin(yaw), math.cos(yaw)
+    # same heading, side by side: the margin on the lateral axis is 1.95 - 1.9
+    init = {"x": np.array([0.0, 1.9 * wx]), "y": np.array([0.0, 1.9 * wy]), "yaw": np.array([yaw, yaw]),
+            "vx": 5 * np.array([math.cos(yaw)] * 2), "vy": 5 * np.array([math.sin(yaw)] * 2),
+            "length": np.array([4.5, 4.0]), "width": np.array([2.0, 1.9]), "valid": np.ones(2, np.uint8)}
+    assert abs(oracle.sat_margin((0, 0, yaw, 4.5, 2.0), (1.9 * wx, 1.9 * wy, yaw, 4.0, 1.9)) - 0.05) < 1e-12
+    log = {f: np.tile(v, (T + 1, 1)) for f, v in init.items()}
+    a = np.array([[0.5, -0.3], [0.1, 0.2], [-0.4, 0.6]])
+    k = np.array([[0.002, -0.005], [0.003, 0.001], [-0.002, 0.004]])
+    off = np.array([0, 2], np.int32)
+    ctrl = np.array([1, 1], np.uint8)
+    ga, gk, loss = oracle.rollout_grad(off, init, a, k, ctrl, log, T, DT)
+    # the loss is dominated by the soft-overlap term (positions stay within a
+    # few metres of the static log, the pair stays within ~0.1 m of touching)
+    assert 0.5 < loss[0] - (np.zeros(0).sum()) and loss[0] < 3 * 6 + 50
+    h = 1e-6
+    for t in range(T):
+        for i in range(n):
+            for arr, g in ((a, ga), (k, gk)):
+                old = arr[t, i]
+                arr[t, i] = old + h
+                lp = oracle.rollout_loss(off, init, a, k, ctrl, log, T, DT)[0]
+                arr[t, i] = old - h
+                lm = oracle.rollout_loss(off, init, a, k, ctrl, log, T, DT)[0]
+                arr[t, i] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - g[t, i]) <= 1e-5 * max(1.0, abs(fd)), (t, i, fd, g[t, i])
+
+
+def test_straight_line_gradient_closed_form():
+    # One controlled object alone (no pair terms), kappa = 0, velocity along
+    # the yaw: x_t = x0 + cos(yaw) sum_{j<t} (v_j dt + a_j dt^2/2), so
+    # dx_t/da_m = cos(yaw) dt^2 (t - 1 - m + 1/2) for m < t, and
+    # dL/da_m = sum_{t>m} 2 [(x_t - xl_t) cos(yaw) + (y_t - yl_t) sin(yaw)] dt^2 (t - m - 1/2).
+    T = 15
+    yaw, v0 = 0.6, 8.0
+    init = {"x": np.array([3.0]), "y": np.array([-2.0]), "yaw": np.array([yaw]),
+            "vx": np.array([v0 * math.cos(yaw)]), "vy": np.array([v0 * math.sin(yaw)]),
+            "length": np.array([4.5]), "width": np.array([2.0]), "valid": np.ones(1, np.uint8)}
+    rng = np.random.default_rng(42)
+    a = rng.uniform(0, 2, (T, 1))
+    k = np.zeros((T, 1))
+    log = {f: np.tile(v, (T + 1, 1)).astype(float) for f, v in init.items()}
+    log["valid"] = np.ones((T + 1, 1), np.uint8)
+    log["x"] = rng.uniform(-5, 5, (T + 1, 1))
+    log["y"] = rng.uniform(-5, 5, (T + 1, 1))
+    ga, gk, loss = oracle.rollout_grad(np.array([0, 1], np.int32), init, a, k, np.ones(1, np.uint8), log, T, DT)
+    v = v0 + np.r_[0.0, np.cumsum(a[:, 0] * DT)]
+    disp = np.r_[0.0, np.cumsum(v[:T] * DT + 0.5 * a[:, 0] * DT ** 2)]
+    x = 3.0 + math.cos(yaw) * disp
+    y = -2.0 + math.sin(yaw) * disp
+    expect = np.zeros(T)
+    for m in range(T):
+        for t in range(m + 1, T + 1):
+            expect[m] += 2 * ((x[t] - log["x"][t, 0]) * math.cos(yaw) + (y[t] - log["y"][t, 0]) * math.sin(yaw)) \
+                * DT ** 2 * (t - m - 0.5)
+    np.testing.assert_allclose(ga[:, 0], expect, rtol=1e-10, atol=1e-12)
+    exp_loss = ((x[1:] - log["x"][1:, 0]) ** 2 + (y[1:] - log["y"][1:, 0]) ** 2).sum()
+    assert abs(loss[0] - exp_loss) < 1e-9
