@@ -1,0 +1,243 @@
+/*
+ * wm.h -- C ABI of the MI355X (gfx950) simulator hot path.
+ *
+ * The library implements the batched simulator step of "Waymax: An
+ * Accelerated, Data-Driven Simulator for Large-Scale Autonomous Driving
+ * Research" (arXiv 2310.08710) with hand-written HIP kernels:
+ *   - kinematic bicycle dynamics, forward and inverse (App. A.1),
+ *   - the per-step metrics of Sec. 3.4: collision (box overlap), off-road
+ *     (side of the nearest oriented road edge) and displacement error,
+ *   - the default observation of Sec. 3.2 (ego frame + k nearest road points),
+ *   - fused multi-step rollouts (Sec. 5.1, Rollout) and their adjoint
+ *     (differentiable simulation, Sec. 1 and Sec. 6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array pointers are DEVICE pointers owned by the caller.  The library
+ *    never allocates, frees or retains caller memory; scratch memory comes
+ *    from the caller-provided workspace (see wm_workspace_bytes).
+ *  - Every call validates its host-visible arguments synchronously, BEFORE
+ *    any launch, and returns a WM_ERR_* code without touching the device on
+ *    failure.  Device array contents (offsets, flags) are trusted.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    the call returns without synchronizing.  Calls contain no host-device
+ *    synchronization, no allocation and no memset, so a sequence of them can
+ *    be captured into a HIP graph.
+ *  - Batches are packed (CSR): scenario s owns objects obj_off[s] ..
+ *    obj_off[s+1]-1 and road points rg_off[s] .. rg_off[s+1]-1 of the global
+ *    arrays.  Objects of different scenarios never interact.
+ *  - States are structure-of-arrays float32 + a uint8 valid flag.  A state
+ *    sequence (logs, trajectories, checkpoints) is time-major: field[t * n + i]
+ *    with n = wm_batch.total_objects.
+ *  - Units: metres, radians, seconds.  Length is measured along the yaw; boxes
+ *    are centred on (x, y).
+ *  - A metric triggers iff its margin is strictly positive.  Margins with no
+ *    defined value (invalid object, no partner, no road edge) are -FLT_MAX.
+ *  - Road-point indices (nearest_idx, rg_idx) are scenario-local.
+ *  - Errors: the return value is WM_OK or a WM_ERR_* code; a thread-local
+ *    message with the detail is available from wm_last_error_message().
+ */
+#ifndef WM_H
+#define WM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define WM_OK 0
+#define WM_ERR_NULL 1        /* a required pointer is NULL */
+#define WM_ERR_RANGE 2       /* a scalar is out of range (S, T, k, E < 1; dt <= 0 or not finite ...) */
+#define WM_ERR_SHAPE 3       /* inconsistent sizes (totals, maxima) */
+#define WM_ERR_WORKSPACE 4   /* workspace missing or smaller than wm_workspace_bytes */
+#define WM_ERR_UNSUPPORTED 5 /* a size beyond what the kernels support (see limits) */
+#define WM_ERR_DEVICE 6      /* a HIP runtime error; the message carries hipGetErrorString */
+
+/* Limits. */
+#define WM_MAX_OBJECTS 1024      /* objects per scenario */
+#define WM_MAX_TOPK 1024         /* k of wm_observe */
+#define WM_MAX_OBSERVE_POINTS 32768 /* road points per scenario for wm_observe */
+
+/* Road-point type of an oriented road edge (Sec. 3.4, Off-Road). */
+#define WM_TYPE_ROAD_EDGE 1
+
+/* A packed batch of scenarios.  The int32 fields are host values; obj_off and
+ * rg_off are device arrays of S+1 non-decreasing entries starting at 0.
+ * max_objects / max_rg_points must be >= every scenario's count (they size
+ * launches and shared memory); total_objects = obj_off[S] and
+ * total_rg_points = rg_off[S]. */
+typedef struct wm_batch {
+    int32_t num_scenarios;
+    int32_t total_objects;
+    int32_t total_rg_points;
+    int32_t max_objects;
+    int32_t max_rg_points;
+    const int32_t *obj_off;
+    const int32_t *rg_off;
+} wm_batch;
+
+/* Dynamic object state (Sec. 3.2: position, rotation, velocity, box
+ * dimensions; plus validity).  Each member points to total_objects entries
+ * (or T * total_objects for a sequence). */
+typedef struct wm_state {
+    float *x, *y, *yaw, *vx, *vy, *length, *width;
+    uint8_t *valid;
+} wm_state;
+
+/* Static road graph (Sec. 3.2; oriented points, Sec. 3.4 Off-Road), one
+ * entry per point: position, unit direction, type (WM_TYPE_ROAD_EDGE for
+ * road edges), validity.  2D: elevation is not used by any metric. */
+typedef struct wm_roadgraph {
+    const float *x, *y, *dir_x, *dir_y;
+    const int8_t *type;
+    const uint8_t *valid;
+} wm_roadgraph;
+
+/* Bicycle actions (App. A.1: acceleration a [m/s^2], curvature kappa [1/m])
+ * plus the control mask of Sec. 4.1 / Sec. 4.3: objects with controlled = 0
+ * replay the log instead.  accel/curvature hold total_objects entries for a
+ * step, T * total_objects (time-major) for a rollout; controlled always holds
+ * total_objects entries (constant over a rollout). */
+typedef struct wm_action {
+    const float *accel, *curvature;
+    const uint8_t *controlled;
+} wm_action;
+
+/* Per-object metrics of one step (Sec. 3.4); T * total_objects entries for a
+ * rollout.  Any member may be NULL (not computed / not written).
+ *   collision       1 iff the box overlaps another valid box of the scenario
+ *   overlap_margin  max over partners of the separating-axis margin
+ *   offroad         1 iff some box corner lies right of its nearest road edge
+ *   offroad_margin  max over the 4 corners of the signed side distance
+ *   log_div         |xy - xy_log| when both are valid, else 0 */
+typedef struct wm_metrics {
+    uint8_t *collision, *offroad;
+    float *overlap_margin, *offroad_margin, *log_div;
+} wm_metrics;
+
+/* Optional launch tuning of the off-road / rollout kernels; NULL selects the
+ * library's choice (autotuned table if wm_autotune has run, else a default).
+ *   unit_objects  objects per work unit (one work-group): 64, 128 or 256
+ *   edge_splits   road-edge ranges scanned in parallel per object: 1, 2, 4, 8 or 16
+ * unit_objects * edge_splits must not exceed 1024. */
+typedef struct wm_tuning {
+    int32_t unit_objects;
+    int32_t edge_splits;
+} wm_tuning;
+
+/* Bytes of device workspace needed by any call on this batch.  T = 0 covers
+ * the single-step calls; a rollout needs its own T and ckpt_every (0 = no
+ * checkpoints).  Returns 0 if the batch is invalid. */
+size_t wm_workspace_bytes(const wm_batch *batch, int32_t T, int32_t ckpt_every);
+
+/* One simulator step (Sec. 4.1 step(state, action); dynamics App. A.1
+ * bicycle forward).  For every object:
+ *   controlled & valid   : bicycle forward with (accel, curvature)
+ *   controlled & invalid : frozen (next = cur)
+ *   not controlled       : next = log_next (log playback, Sec. 4.3)
+ * Metrics, if m != NULL, are evaluated on the successor state `next`
+ * (collision and off-road need the whole scenario; off-road is skipped when
+ * rg == NULL).  `next` must not alias `cur`.  Workspace: wm_workspace_bytes(batch, 0, 0)
+ * when off-road metrics are requested, else may be NULL. */
+int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act,
+            const wm_state *log_next, const wm_roadgraph *rg, float dt, wm_state *next,
+            wm_metrics *m, void *ws, size_t ws_bytes, void *stream);
+
+/* Expert action by inverse kinematics (App. A.1, inverse kinematics
+ * equation; Sec. 5.2 Expert): a = (|v'| - |v|)/dt,
+ * kappa = wrap(atan2(vy', vx') - yaw) / (|v| dt + a dt^2/2), kappa = 0 when
+ * that distance is below 1e-6 m.  valid_out = both states valid (a = kappa = 0
+ * otherwise).  Outputs hold total_objects entries; valid_out may be NULL. */
+int wm_inverse_action(const wm_batch *batch, const wm_state *cur, const wm_state *next, float dt,
+                      float *accel, float *curvature, uint8_t *valid_out, void *stream);
+
+/* Collision metric (Sec. 3.4, Collision: 2D top-down box overlap) by the
+ * separating-axis test.  For every object: collision (u8) and max_margin
+ * (f32), either may be NULL.  Optionally the full per-scenario margin / mask
+ * matrices: block s starts at pair_off[s] (device int64 [S+1]) and holds
+ * N_s x N_s row-major entries (diagonal and pairs with an invalid box:
+ * margin -FLT_MAX, mask 0).  margin and mask may be NULL; pair_off is required
+ * iff one of them is given.  The matrix is exactly symmetric. */
+int wm_overlap(const wm_batch *batch, const wm_state *st, const int64_t *pair_off, float *margin,
+               uint8_t *mask, uint8_t *collision, float *max_margin, void *stream);
+
+/* Off-road metric (Sec. 3.4, Off-Road).  For each of the 4 corners of every
+ * valid box (front-left, front-right, rear-right, rear-left) the nearest valid
+ * road-edge point q (2D distance, ties to the lower index) decides the side:
+ * s = -cross(dir_q, corner - q) > 0 means off road.  margin = max_k s_k,
+ * offroad = margin > 0.  nearest_idx (int32 [4 * total_objects], may be NULL)
+ * receives the scenario-local index per corner (-1: none).  Workspace:
+ * wm_workspace_bytes(batch, 0, 0).  `tune` may be NULL. */
+int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg, uint8_t *offroad,
+               float *margin, int32_t *nearest_idx, const wm_tuning *tune, void *ws, size_t ws_bytes,
+               void *stream);
+
+/* Default observation (Sec. 3.2): for each of the E egos of every scenario
+ * (ego: device int32 [S * E], global object ids):
+ *   rg_idx   int32 [S*E*k]: the k valid road points (any type) nearest to the
+ *            ego centre, ascending by (d2, index) with the binary32 key
+ *            d2 = fl(fl(dx*dx) + fl(dy*dy)), dx = fl(qx - ex); -1 padding.
+ *   rg_feat  f32 [S*E*k*4] or NULL: R(-yaw_e)(q - p_e), R(-yaw_e) dir_q; 0 padding.
+ *   obj_feat f32 [S*E*max_objects*8] or NULL: for object j of the scenario,
+ *            R(-yaw_e)(p_j - p_e), wrap(yaw_j - yaw_e), R(-yaw_e) v_j, length,
+ *            width, 1; zeros for invalid or padded slots.
+ * An invalid ego yields -1 / zeros.  Limits: k <= WM_MAX_TOPK,
+ * max_rg_points <= WM_MAX_OBSERVE_POINTS. */
+int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg, const int32_t *ego,
+               int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream);
+
+/* Fused rollout of T steps (Sec. 5.1 Rollout; each step as wm_step with all
+ * metrics, evaluated on the successor state).  One persistent kernel runs all
+ * T steps of every (scenario, object slice) work unit, taking units from a
+ * device queue in descending cost order.
+ *   init       state at the current time (row 0 of the logs)
+ *   act_seq    actions [T][n]; controlled [n]
+ *   log_seq    logged states [T+1][n], row 0 = the initial time
+ *   rg         road graph (off-road metrics); may be NULL (no off-road)
+ *   ckpt       [ceil(T/ckpt_every)][n] states at t = 0, c, 2c, ... or NULL
+ *   traj       [T][n] successor states or NULL
+ *   met_seq    [T][n] metrics or NULL (members may be NULL)
+ *   loss       [S] training loss or NULL: sum over t of
+ *                sum_{controlled i, valid in sim and log} |p_i - p_i^log|^2
+ *              + sum_{i<j valid, i or j controlled} sigmoid(margin_ij / 0.1 m)
+ * Workspace: wm_workspace_bytes(batch, T, ckpt_every). */
+int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
+               const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, int32_t ckpt_every,
+               wm_state *ckpt, wm_state *traj, wm_metrics *met_seq, float *loss, const wm_tuning *tune,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of wm_rollout's loss with respect to the actions (differentiable
+ * simulation, Sec. 1 / Sec. 6), by a hand-written reverse sweep that
+ * recomputes each checkpoint segment.  dloss [S] scales each scenario's loss
+ * gradient.  grad_accel / grad_curvature [T][n] are overwritten (zero for
+ * uncontrolled or invalid objects).  ckpt must come from wm_rollout with the
+ * same inputs and ckpt_every.  Non-smooth points: sgn(0) = +1, the lowest
+ * separating axis wins a tie, d|v|/dv = 0 at v = 0.  Workspace:
+ * wm_workspace_bytes(batch, T, ckpt_every). */
+int wm_rollout_backward(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
+                        const wm_state *log_seq, int32_t T, float dt, int32_t ckpt_every,
+                        const wm_state *ckpt, const float *dloss, float *grad_accel, float *grad_curvature,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* Measure the rollout for each candidate tuning on this batch (real launches
+ * on `stream`, synchronizing) and remember the fastest for batches with the
+ * same (max_objects, max_rg_points) bucket.  best (host) receives it; may be
+ * NULL.  Not capturable. */
+int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
+                const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, void *ws,
+                size_t ws_bytes, wm_tuning *best, void *stream);
+
+/* Static description of a return code. */
+const char *wm_error_string(int code);
+
+/* Detail of the last error returned on the calling thread ("" if none). */
+const char *wm_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WM_H */

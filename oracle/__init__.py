@@ -245,6 +245,18 @@ def rollout(obj_off, rg_off, init, accel, curvature, controlled, log_seq, rg, T:
     return out
 
 
+def state_loss(obj_off, state, log, controlled):
+    """Loss terms of one state against the log at the same step, per scenario."""
+    off = _i32(obj_off)
+    S = off.shape[0] - 1
+    st, lg = OState(state), OState(log)
+    c = _u8(controlled)
+    out = np.zeros(S)
+    lib().or_state_loss(C.c_int(S), _p(off, C.c_int32), C.byref(st.c), C.byref(lg.c), _p(c, C.c_uint8),
+                        _p(out, C.c_double))
+    return out
+
+
 def rollout_loss(obj_off, init, accel, curvature, controlled, log_seq, T: int, dt: float):
     """Per-scenario training loss of a rollout (the loss read for the
     paper's differentiable-simulation use, Sec. 1 / Sec. 6)."""

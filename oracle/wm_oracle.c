@@ -499,6 +499,14 @@ static double step_loss(int o, int N, const or_state *st, const or_state *log, c
     return L;
 }
 
+/* Loss terms of one state against its log, per scenario (loss[S]). */
+void or_state_loss(int S, const int32_t *obj_off, const or_state *st, const or_state *log,
+                   const uint8_t *controlled, double *loss)
+{
+    for (int s = 0; s < S; ++s)
+        loss[s] = step_loss(obj_off[s], obj_off[s + 1] - obj_off[s], st, log, controlled);
+}
+
 /* ------------------------------------------------------------------------
  * Rollout (Sec. 5.1, Rollout; Sec. 4.1 step): starting from init (the state
  * at the current time), for t = 1..T

@@ -1,0 +1,466 @@
+// wm_api.cpp -- the C ABI declared in include/wm.h: argument validation,
+// workspace carving, launch configuration, the rollout autotuner and error
+// reporting.  Validation never touches the device: every check below runs on
+// host-visible values before the first launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "../../include/wm.h"
+#include "wm_internal.h"
+
+namespace {
+
+thread_local std::string g_msg;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_msg = buf;
+    return code;
+}
+
+int ok()
+{
+    g_msg.clear();
+    return WM_OK;
+}
+
+int device_status(const char *where)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(WM_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+    return ok();
+}
+
+#define CHECK(expr)                   \
+    do {                              \
+        const int _rc = (expr);       \
+        if (_rc != WM_OK)             \
+            return _rc;               \
+    } while (0)
+
+int check_batch(const wm_batch *b)
+{
+    if (!b)
+        return fail(WM_ERR_NULL, "batch is NULL");
+    if (!b->obj_off || !b->rg_off)
+        return fail(WM_ERR_NULL, "batch offsets are NULL");
+    if (b->num_scenarios < 1)
+        return fail(WM_ERR_RANGE, "num_scenarios = %d < 1", b->num_scenarios);
+    if (b->total_objects < 0 || b->total_rg_points < 0 || b->max_objects < 0 || b->max_rg_points < 0)
+        return fail(WM_ERR_SHAPE, "negative batch size");
+    if (b->max_objects > b->total_objects || b->max_rg_points > b->total_rg_points)
+        return fail(WM_ERR_SHAPE, "max_objects/max_rg_points exceed the totals");
+    if (b->max_objects > WM_MAX_OBJECTS)
+        return fail(WM_ERR_UNSUPPORTED, "max_objects = %d > %d", b->max_objects, WM_MAX_OBJECTS);
+    return WM_OK;
+}
+
+int check_state(const wm_state *s, const char *name)
+{
+    if (!s)
+        return fail(WM_ERR_NULL, "%s is NULL", name);
+    if (!s->x || !s->y || !s->yaw || !s->vx || !s->vy || !s->length || !s->width || !s->valid)
+        return fail(WM_ERR_NULL, "%s has a NULL member", name);
+    return WM_OK;
+}
+
+int check_rg(const wm_roadgraph *r)
+{
+    if (!r->x || !r->y || !r->dir_x || !r->dir_y || !r->type || !r->valid)
+        return fail(WM_ERR_NULL, "roadgraph has a NULL member");
+    return WM_OK;
+}
+
+int check_dt(float dt)
+{
+    if (!(dt > 0.f) || !std::isfinite(dt))
+        return fail(WM_ERR_RANGE, "dt = %g must be finite and > 0", (double)dt);
+    return WM_OK;
+}
+
+int check_ws(const void *ws, size_t have, size_t need)
+{
+    if (need == 0)
+        return WM_OK;
+    if (!ws)
+        return fail(WM_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+    if (have < need)
+        return fail(WM_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", have, need);
+    return WM_OK;
+}
+
+struct Tune {
+    int G, CW;
+};
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, Tune> g_tune_table;
+
+std::pair<int, int> tune_key(const wm_batch *b)
+{
+    int ob = 0, pb = 0;
+    while ((1 << ob) < b->max_objects)
+        ++ob;
+    while ((1 << pb) < b->max_rg_points)
+        ++pb;
+    return {ob, pb};
+}
+
+int resolve_tune(const wm_batch *b, const wm_tuning *t, Tune *out)
+{
+    if (t) {
+        const int U = t->unit_objects, G = t->edge_splits;
+        if (U != 64 && U != 128 && U != 256)
+            return fail(WM_ERR_RANGE, "unit_objects = %d not in {64, 128, 256}", U);
+        if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16)
+            return fail(WM_ERR_RANGE, "edge_splits = %d not in {1, 2, 4, 8, 16}", G);
+        if (U * G > 1024)
+            return fail(WM_ERR_RANGE, "unit_objects * edge_splits = %d > 1024", U * G);
+        out->G = G;
+        out->CW = U / 64;
+        return WM_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_table.find(tune_key(b));
+    if (it != g_tune_table.end()) {
+        *out = it->second;
+    } else {
+        out->G = 8;
+        out->CW = 1;
+    }
+    return WM_OK;
+}
+
+size_t workspace_bytes(const wm_batch *b, int T, int K)
+{
+    return wm::ws_layout(b->num_scenarios, b->total_objects, b->total_rg_points, T, K).total;
+}
+
+} // namespace
+
+extern "C" {
+
+size_t wm_workspace_bytes(const wm_batch *batch, int32_t T, int32_t ckpt_every)
+{
+    if (check_batch(batch) != WM_OK || T < 0 || ckpt_every < 0)
+        return 0;
+    return workspace_bytes(batch, T, ckpt_every);
+}
+
+const char *wm_error_string(int code)
+{
+    switch (code) {
+    case WM_OK: return "ok";
+    case WM_ERR_NULL: return "a required pointer is NULL";
+    case WM_ERR_RANGE: return "a scalar argument is out of range";
+    case WM_ERR_SHAPE: return "inconsistent sizes";
+    case WM_ERR_WORKSPACE: return "workspace missing or too small";
+    case WM_ERR_UNSUPPORTED: return "size not supported by the kernels";
+    case WM_ERR_DEVICE: return "HIP runtime error";
+    default: return "unknown error code";
+    }
+}
+
+const char *wm_last_error_message(void) { return g_msg.c_str(); }
+
+int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+            const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
+            void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(cur, "cur"));
+    CHECK(check_state(log_next, "log_next"));
+    CHECK(check_state(next, "next"));
+    if (!act || !act->accel || !act->curvature || !act->controlled)
+        return fail(WM_ERR_NULL, "action is NULL or has a NULL member");
+    CHECK(check_dt(dt));
+    if (next->x == cur->x)
+        return fail(WM_ERR_RANGE, "next must not alias cur");
+    const bool want_off = m && rg && (m->offroad || m->offroad_margin);
+    if (want_off)
+        CHECK(check_rg(rg));
+    const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
+    if (want_off)
+        CHECK(check_ws(ws, ws_bytes, L.total));
+    hipStream_t st = (hipStream_t)stream;
+    wm::StepArgs a{batch->obj_off, *cur, *act, *log_next, *next, dt, m ? m->log_div : nullptr};
+    wm::launch_dynamics(*batch, a, st);
+    if (m && (m->collision || m->overlap_margin)) {
+        wm::OverlapArgs o{batch->obj_off, *next, nullptr, nullptr, nullptr, m->collision, m->overlap_margin,
+                          batch->max_objects, 64};
+        wm::launch_overlap(*batch, o, st);
+    }
+    if (want_off) {
+        unsigned char *w = (unsigned char *)ws;
+        Tune tn;
+        CHECK(resolve_tune(batch, nullptr, &tn));
+        tn.CW = 1;
+        if (tn.G > 16)
+            tn.G = 16;
+        wm::launch_compact_edges(*batch, *rg, w, L, st);
+        wm::OffroadArgs o{batch->obj_off, batch->rg_off, *next, (const float2 *)(w + L.exy),
+                          (const float2 *)(w + L.edir), (const int32_t *)(w + L.eidx),
+                          (const int32_t *)(w + L.ecount), m->offroad, m->offroad_margin, nullptr, tn.G, tn.CW};
+        wm::launch_offroad(*batch, o, st);
+    }
+    return device_status("wm_step");
+}
+
+int wm_inverse_action(const wm_batch *batch, const wm_state *cur, const wm_state *next, float dt, float *accel,
+                      float *curvature, uint8_t *valid_out, void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(cur, "cur"));
+    CHECK(check_state(next, "next"));
+    if (!accel || !curvature)
+        return fail(WM_ERR_NULL, "accel/curvature output is NULL");
+    CHECK(check_dt(dt));
+    if (batch->total_objects > 0)
+        wm::launch_inverse(batch->total_objects, *cur, *next, dt, accel, curvature, valid_out, (hipStream_t)stream);
+    return device_status("wm_inverse_action");
+}
+
+int wm_overlap(const wm_batch *batch, const wm_state *st, const int64_t *pair_off, float *margin, uint8_t *mask,
+               uint8_t *collision, float *max_margin, void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(st, "state"));
+    if ((margin || mask) && !pair_off)
+        return fail(WM_ERR_NULL, "pair_off is NULL but a margin/mask matrix was requested");
+    if (!margin && !mask && !collision && !max_margin)
+        return ok();
+    wm::OverlapArgs o{batch->obj_off, *st, pair_off, margin, mask, collision, max_margin, batch->max_objects, 64};
+    wm::launch_overlap(*batch, o, (hipStream_t)stream);
+    return device_status("wm_overlap");
+}
+
+int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg, uint8_t *offroad, float *margin,
+               int32_t *nearest_idx, const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(st, "state"));
+    if (!rg)
+        return fail(WM_ERR_NULL, "roadgraph is NULL");
+    CHECK(check_rg(rg));
+    Tune tn;
+    CHECK(resolve_tune(batch, tune, &tn));
+    const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
+    CHECK(check_ws(ws, ws_bytes, L.total));
+    if (!offroad && !margin && !nearest_idx)
+        return ok();
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)ws;
+    wm::launch_compact_edges(*batch, *rg, w, L, s);
+    wm::OffroadArgs o{batch->obj_off, batch->rg_off, *st, (const float2 *)(w + L.exy), (const float2 *)(w + L.edir),
+                      (const int32_t *)(w + L.eidx), (const int32_t *)(w + L.ecount), offroad, margin, nearest_idx,
+                      tn.G, tn.CW};
+    wm::launch_offroad(*batch, o, s);
+    return device_status("wm_offroad");
+}
+
+int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg, const int32_t *ego, int32_t E,
+               int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(st, "state"));
+    if (!rg)
+        return fail(WM_ERR_NULL, "roadgraph is NULL");
+    CHECK(check_rg(rg));
+    if (!ego || !rg_idx)
+        return fail(WM_ERR_NULL, "ego or rg_idx is NULL");
+    if (E < 1 || k < 1)
+        return fail(WM_ERR_RANGE, "E = %d and k = %d must be >= 1", E, k);
+    if (k > WM_MAX_TOPK)
+        return fail(WM_ERR_UNSUPPORTED, "k = %d > %d", k, WM_MAX_TOPK);
+    if (batch->max_rg_points > WM_MAX_OBSERVE_POINTS)
+        return fail(WM_ERR_UNSUPPORTED, "max_rg_points = %d > %d", batch->max_rg_points, WM_MAX_OBSERVE_POINTS);
+    if ((long)batch->num_scenarios * E > 0x7fffffffL / (k > 8 ? k : 8))
+        return fail(WM_ERR_UNSUPPORTED, "S * E * k too large");
+    wm::ObserveArgs a{batch->obj_off, batch->rg_off, *st, *rg, ego, E, k, batch->max_objects, rg_idx, rg_feat,
+                      obj_feat};
+    wm::launch_observe(*batch, a, (hipStream_t)stream);
+    return device_status("wm_observe");
+}
+
+static int rollout_checks(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
+                          const wm_state *log_seq, int32_t T, float dt, int32_t ckpt_every)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(init, "init"));
+    CHECK(check_state(log_seq, "log_seq"));
+    if (!act_seq || !act_seq->accel || !act_seq->curvature || !act_seq->controlled)
+        return fail(WM_ERR_NULL, "act_seq is NULL or has a NULL member");
+    if (T < 1)
+        return fail(WM_ERR_RANGE, "T = %d < 1", T);
+    if (ckpt_every < 0)
+        return fail(WM_ERR_RANGE, "ckpt_every = %d < 0", ckpt_every);
+    if ((long long)(T + 1) * batch->total_objects > 0x7fffffffLL)
+        return fail(WM_ERR_UNSUPPORTED, "(T + 1) * total_objects exceeds int32 indexing");
+    return check_dt(dt);
+}
+
+int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act_seq, const wm_state *log_seq,
+               const wm_roadgraph *rg, int32_t T, float dt, int32_t ckpt_every, wm_state *ckpt, wm_state *traj,
+               wm_metrics *met_seq, float *loss, const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)
+{
+    CHECK(rollout_checks(batch, init, act_seq, log_seq, T, dt, ckpt_every));
+    if (rg)
+        CHECK(check_rg(rg));
+    if (ckpt) {
+        CHECK(check_state(ckpt, "ckpt"));
+        if (ckpt_every < 1)
+            return fail(WM_ERR_RANGE, "ckpt given but ckpt_every = %d < 1", ckpt_every);
+    }
+    if (traj)
+        CHECK(check_state(traj, "traj"));
+    Tune tn;
+    CHECK(resolve_tune(batch, tune, &tn));
+    const wm::WsLayout L =
+        wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, T, ckpt_every);
+    CHECK(check_ws(ws, ws_bytes, L.total));
+    const size_t lds = wm::rollout_lds_bytes(batch->max_objects, tn.G, tn.CW);
+    if (lds > 160 * 1024)
+        return fail(WM_ERR_UNSUPPORTED, "rollout needs %zu bytes of LDS", lds);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)ws;
+    if (rg)
+        wm::launch_compact_edges(*batch, *rg, w, L, s);
+    wm::launch_build_units(*batch, 64 * tn.CW, rg ? (const int32_t *)(w + L.ecount) : nullptr, w, L, s);
+    wm::RollArgs a{};
+    a.S = batch->num_scenarios;
+    a.n = batch->total_objects;
+    a.T = T;
+    a.ckpt_every = ckpt_every;
+    a.maxN = batch->max_objects;
+    a.G = tn.G;
+    a.CW = tn.CW;
+    a.dt = dt;
+    a.obj_off = batch->obj_off;
+    a.rg_off = batch->rg_off;
+    a.init = *init;
+    a.act = *act_seq;
+    a.log = *log_seq;
+    a.has_rg = rg != nullptr;
+    a.has_ckpt = ckpt != nullptr;
+    a.has_traj = traj != nullptr;
+    a.want_loss = loss != nullptr;
+    a.exy = (const float2 *)(w + L.exy);
+    a.edir = (const float2 *)(w + L.edir);
+    a.eidx = (const int32_t *)(w + L.eidx);
+    a.ecount = (const int32_t *)(w + L.ecount);
+    if (ckpt)
+        a.ckpt = *ckpt;
+    if (traj)
+        a.traj = *traj;
+    if (met_seq)
+        a.met = *met_seq;
+    a.lossp = (float *)(w + L.lossp);
+    a.uoff = (const int32_t *)(w + L.uoff);
+    a.units = (const int2 *)(w + L.units);
+    a.counter = (int32_t *)(w + L.counter);
+    const int U = 64 * tn.CW;
+    const int bound = batch->total_objects / U + batch->num_scenarios;
+    const int grid = wm::rollout_grid(tn.G, tn.CW, batch->max_objects, bound);
+    wm::launch_rollout(a, grid, s);
+    if (loss)
+        wm::launch_loss_reduce(batch->num_scenarios, a.uoff, a.lossp, loss, s);
+    return device_status("wm_rollout");
+}
+
+int wm_rollout_backward(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
+                        const wm_state *log_seq, int32_t T, float dt, int32_t ckpt_every, const wm_state *ckpt,
+                        const float *dloss, float *grad_accel, float *grad_curvature, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    CHECK(rollout_checks(batch, init, act_seq, log_seq, T, dt, ckpt_every));
+    CHECK(check_state(ckpt, "ckpt"));
+    if (ckpt_every < 1)
+        return fail(WM_ERR_RANGE, "ckpt_every = %d < 1", ckpt_every);
+    if (!dloss || !grad_accel || !grad_curvature)
+        return fail(WM_ERR_NULL, "dloss or a gradient output is NULL");
+    const wm::WsLayout L =
+        wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, T, ckpt_every);
+    CHECK(check_ws(ws, ws_bytes, L.total));
+    wm::BackwardArgs a{};
+    a.S = batch->num_scenarios;
+    a.n = batch->total_objects;
+    a.T = T;
+    a.K = ckpt_every;
+    a.maxN = batch->max_objects;
+    a.dt = dt;
+    a.obj_off = batch->obj_off;
+    a.init = *init;
+    a.act = *act_seq;
+    a.log = *log_seq;
+    a.ckpt = *ckpt;
+    a.dloss = dloss;
+    a.grad_a = grad_accel;
+    a.grad_k = grad_curvature;
+    a.seg = (float *)((unsigned char *)ws + L.seg);
+    wm::launch_backward(a, (hipStream_t)stream);
+    return device_status("wm_rollout_backward");
+}
+
+int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *act_seq, const wm_state *log_seq,
+                const wm_roadgraph *rg, int32_t T, float dt, void *ws, size_t ws_bytes, wm_tuning *best,
+                void *stream)
+{
+    CHECK(rollout_checks(batch, init, act_seq, log_seq, T, dt, 0));
+    const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, T, 0);
+    CHECK(check_ws(ws, ws_bytes, L.total));
+    static const int cand[][2] = {{64, 2}, {64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8}, {256, 2}, {256, 4}};
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return device_status("wm_autotune: event");
+    float best_ms = 1e30f;
+    wm_tuning pick{64, 8};
+    for (const auto &c : cand) {
+        wm_tuning t{c[0], c[1]};
+        if (wm::rollout_lds_bytes(batch->max_objects, t.edge_splits, t.unit_objects / 64) > 160 * 1024)
+            continue;
+        int rc = wm_rollout(batch, init, act_seq, log_seq, rg, T, dt, 0, nullptr, nullptr, nullptr, nullptr, &t, ws,
+                            ws_bytes, stream);
+        if (rc != WM_OK)
+            break;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < 2; ++r)
+            wm_rollout(batch, init, act_seq, log_seq, rg, T, dt, 0, nullptr, nullptr, nullptr, nullptr, &t, ws,
+                       ws_bytes, stream);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            pick = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    const int rc = device_status("wm_autotune");
+    if (rc != WM_OK)
+        return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_table[tune_key(batch)] = Tune{pick.edge_splits, pick.unit_objects / 64};
+    }
+    if (best)
+        *best = pick;
+    return ok();
+}
+
+} // extern "C"

@@ -1,0 +1,131 @@
+// wm_internal.h -- argument blocks shared by the kernels and the host API,
+// the workspace layout and the launch entry points of wm_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/wm.h"
+
+namespace wm {
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct StepArgs {
+    const int32_t *obj_off;
+    wm_state cur;
+    wm_action act;
+    wm_state log_next;
+    wm_state next;
+    float dt;
+    float *log_div;
+};
+
+struct OverlapArgs {
+    const int32_t *obj_off;
+    wm_state st;
+    const int64_t *pair_off;
+    float *margin;
+    uint8_t *mask;
+    uint8_t *collision;
+    float *max_margin;
+    int maxN;
+    int U;
+};
+
+struct OffroadArgs {
+    const int32_t *obj_off, *rg_off;
+    wm_state st;
+    const float2 *exy, *edir;
+    const int32_t *eidx, *ecount;
+    uint8_t *offroad;
+    float *margin;
+    int32_t *nearest;
+    int G, CW;
+};
+
+struct RollArgs {
+    int S, n, T, ckpt_every, maxN, G, CW;
+    float dt;
+    const int32_t *obj_off, *rg_off;
+    wm_state init;
+    wm_action act;
+    wm_state log;
+    int has_rg, has_ckpt, has_traj, want_loss;
+    const float2 *exy, *edir;
+    const int32_t *eidx, *ecount;
+    wm_state ckpt, traj;
+    wm_metrics met;
+    float *lossp;
+    const int32_t *uoff;
+    const int2 *units;
+    int32_t *counter;
+};
+
+struct ObserveArgs {
+    const int32_t *obj_off, *rg_off;
+    wm_state st;
+    wm_roadgraph rg;
+    const int32_t *ego;
+    int E, k, maxN;
+    int32_t *rg_idx;
+    float *rg_feat, *obj_feat;
+};
+
+struct BackwardArgs {
+    int S, n, T, K, maxN;
+    float dt;
+    const int32_t *obj_off;
+    wm_state init;
+    wm_action act;
+    wm_state log;
+    wm_state ckpt;
+    const float *dloss;
+    float *grad_a, *grad_k;
+    float *seg;      // [K+1][5][n] recomputed segment states (x, y, yaw, vx, vy)
+};
+
+// Workspace sections (byte offsets, each 256-aligned).
+struct WsLayout {
+    size_t ecount, exy, edir, eidx, uoff, units, lossp, counter, seg, total;
+};
+
+inline WsLayout ws_layout(int S, int n, int P, int T, int K)
+{
+    const size_t cap = (size_t)P + (size_t)S * 32 + 32;
+    WsLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+    L.ecount = take(sizeof(int32_t) * (size_t)S);
+    L.exy = take(sizeof(float) * 2 * cap);
+    L.edir = take(sizeof(float) * 2 * cap);
+    L.eidx = take(sizeof(int32_t) * cap);
+    L.uoff = take(sizeof(int32_t) * ((size_t)S + 1));
+    L.units = take(sizeof(int32_t) * 2 * ((size_t)n + 1));
+    L.lossp = take(sizeof(float) * ((size_t)n + 1));
+    L.counter = take(sizeof(int32_t) * 16);
+    L.seg = (T > 0 && K > 0) ? take(sizeof(float) * 5 * (size_t)(K + 1) * (size_t)n) : o;
+    L.total = o;
+    return L;
+}
+
+// Launchers (wm_kernels.hip).  They only enqueue; errors surface through
+// hipGetLastError in the caller.
+void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned char *ws, const WsLayout &L,
+                          hipStream_t st);
+void launch_build_units(const wm_batch &b, int U, const int32_t *ecount, unsigned char *ws, const WsLayout &L,
+                        hipStream_t st);
+void launch_dynamics(const wm_batch &b, const StepArgs &a, hipStream_t st);
+void launch_inverse(int n, const wm_state &cur, const wm_state &nxt, float dt, float *accel, float *curv,
+                    uint8_t *vout, hipStream_t st);
+void launch_overlap(const wm_batch &b, const OverlapArgs &a, hipStream_t st);
+void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st);
+size_t rollout_lds_bytes(int maxN, int G, int CW);
+int rollout_grid(int G, int CW, int maxN, int n_units_bound);
+void launch_rollout(const RollArgs &a, int grid, hipStream_t st);
+void launch_loss_reduce(int S, const int32_t *uoff, const float *lossp, float *loss, hipStream_t st);
+void launch_observe(const wm_batch &b, const ObserveArgs &a, hipStream_t st);
+void launch_backward(const BackwardArgs &a, hipStream_t st);
+
+} // namespace wm

@@ -1,0 +1,727 @@
+// wm_kernels.hip -- HIP kernels of the simulator hot path for gfx950.
+//
+// Kernels (all float32):
+//   k_compact_edges  road-graph preparation: valid road-edge points of each
+//                    scenario packed in index order, padded to whole chunks
+//   k_build_units    work-unit table (scenario, object slice) in descending
+//                    cost order for the persistent rollout kernel
+//   k_dynamics       one plain step: bicycle forward / playback / frozen (+ log divergence)
+//   k_inverse        bicycle inverse kinematics
+//   k_overlap        plain collision metric (+ optional margin matrix)
+//   k_offroad        plain off-road metric
+//   k_rollout        persistent fused rollout: T steps of dynamics + all metrics
+//                    + training loss + checkpoints per work unit
+//   k_loss_reduce    deterministic per-scenario sum of the loss partials
+//   k_observe, k_rollout_backward live in their own sections below.
+#include "wm_device.h"
+#include "wm_internal.h"
+
+namespace wm {
+
+// ---------------------------------------------------------------------------
+// Road-edge compaction.  Scenario s owns workspace slots
+// [rg_off[s] + s * kChunk, rg_off[s+1] + (s+1) * kChunk): its E_s valid road
+// edges in index order, then +inf points up to a whole number of chunks.
+// ---------------------------------------------------------------------------
+template <int BT>
+__global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict__ rg_off, wm_roadgraph rg,
+                                                     float2 *__restrict__ exy, float2 *__restrict__ edir,
+                                                     int32_t *__restrict__ eidx, int32_t *__restrict__ ecount)
+{
+    __shared__ int wave_tot[BT / 64];
+    __shared__ int run;
+    const int s = blockIdx.x;
+    const int p0 = rg_off[s], p1 = rg_off[s + 1];
+    const int base = p0 + s * kChunk;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0)
+        run = 0;
+    __syncthreads();
+    for (int j0 = p0; j0 < p1; j0 += BT) {
+        const int j = j0 + threadIdx.x;
+        const bool f = j < p1 && rg.valid[j] && rg.type[j] == WM_TYPE_ROAD_EDGE;
+        const uint64_t m = __ballot(f);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wave_tot[w] = __popcll(m);
+        __syncthreads();
+        int off = run, total = 0;
+        for (int i = 0; i < BT / 64; ++i) {
+            off += (i < w) ? wave_tot[i] : 0;
+            total += wave_tot[i];
+        }
+        if (f) {
+            const int o = base + off + pre;
+            exy[o] = make_float2(rg.x[j], rg.y[j]);
+            edir[o] = make_float2(rg.dir_x[j], rg.dir_y[j]);
+            eidx[o] = j - p0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            run += total;
+        __syncthreads();
+    }
+    const int E = run;
+    const int padded = (E + kChunk - 1) / kChunk * kChunk;
+    for (int j = E + threadIdx.x; j < padded; j += BT) {
+        exy[base + j] = make_float2(__builtin_inff(), __builtin_inff());
+        edir[base + j] = make_float2(0.f, 0.f);
+        eidx[base + j] = -1;
+    }
+    if (threadIdx.x == 0)
+        ecount[s] = E;
+}
+
+// ---------------------------------------------------------------------------
+// Work units of the persistent rollout: scenario s is cut into
+// ceil(N_s / U) slices of U objects.  Unit ids are scenario-major
+// (uoff[s] + slice); the queue holds them in descending cost order
+// (cost = slice objects x padded road edges), a longest-first schedule.
+// Also resets the queue counter.  One block of 1024 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict__ obj_off,
+                                                      const int32_t *__restrict__ ecount, int S, int U,
+                                                      int32_t *__restrict__ uoff, int2 *__restrict__ units,
+                                                      int32_t *__restrict__ counter)
+{
+    constexpr int NB = 1024;
+    __shared__ int sh[1024];
+    __shared__ unsigned long long maxcost;
+    __shared__ int start[NB];
+    __shared__ int carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        carry = 0;
+        maxcost = 1;
+    }
+    start[tid] = 0;
+    __syncthreads();
+    // uoff: exclusive scan of units per scenario
+    for (int s0 = 0; s0 < S; s0 += 1024) {
+        const int s = s0 + tid;
+        int nu = 0;
+        if (s < S) {
+            const int N = obj_off[s + 1] - obj_off[s];
+            nu = (N + U - 1) / U;
+        }
+        sh[tid] = nu;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int v = tid >= d ? sh[tid - d] : 0;
+            __syncthreads();
+            sh[tid] += v;
+            __syncthreads();
+        }
+        if (s < S)
+            uoff[s] = carry + sh[tid] - nu;
+        __syncthreads();
+        if (tid == 1023)
+            carry += sh[1023];
+        __syncthreads();
+    }
+    const int total = carry;
+    if (tid == 0) {
+        uoff[S] = total;
+        counter[0] = 0;
+        counter[1] = total;
+    }
+    // costs
+    for (int s = tid; s < S; s += 1024) {
+        const int N = obj_off[s + 1] - obj_off[s];
+        const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
+                                             : (unsigned long long)kChunk;
+        for (int sl = 0; sl * U < N; ++sl) {
+            const unsigned long long c = (unsigned long long)min(U, N - sl * U) * ep;
+            atomicMax(&maxcost, c);
+        }
+    }
+    __syncthreads();
+    const unsigned long long mc = maxcost;
+    for (int s = tid; s < S; s += 1024) {
+        const int N = obj_off[s + 1] - obj_off[s];
+        const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
+                                             : (unsigned long long)kChunk;
+        for (int sl = 0; sl * U < N; ++sl) {
+            const unsigned long long c = (unsigned long long)min(U, N - sl * U) * ep;
+            const int b = (int)((c * (NB - 1)) / mc);
+            atomicAdd(&start[b], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive scan in descending bucket order: bucket NB-1 first
+    sh[tid] = start[NB - 1 - tid];
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int v = tid >= d ? sh[tid - d] : 0;
+        __syncthreads();
+        sh[tid] += v;
+        __syncthreads();
+    }
+    const int excl = sh[tid] - start[NB - 1 - tid];
+    __syncthreads();
+    start[NB - 1 - tid] = excl;
+    __syncthreads();
+    for (int s = tid; s < S; s += 1024) {
+        const int N = obj_off[s + 1] - obj_off[s];
+        const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
+                                             : (unsigned long long)kChunk;
+        for (int sl = 0; sl * U < N; ++sl) {
+            const unsigned long long c = (unsigned long long)min(U, N - sl * U) * ep;
+            const int b = (int)((c * (NB - 1)) / mc);
+            const int pos = atomicAdd(&start[b], 1);
+            units[pos] = make_int2(s, sl);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shared per-unit pieces used by the plain and the fused kernels.  The
+// objects of one scenario live in LDS (ObjLds, scenario-local index).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Box lds_box(const ObjLds &L, int i)
+{
+    Box b;
+    b.x = L.x[i];
+    b.y = L.y[i];
+    b.c = L.c[i];
+    b.s = L.s[i];
+    b.hl = 0.5f * L.len[i];
+    b.hw = 0.5f * L.wid[i];
+    return b;
+}
+
+__device__ __forceinline__ float sigmoidf(float z)
+{
+    return 1.0f / (1.0f + expf(-z));
+}
+
+// Overlap of slice objects i0 .. i0+Ns-1 against all N objects.  Thread
+// (il = tid % U, part = tid / U) takes partners j = part, part + P, ...;
+// per-thread maxima go to red[part * U + il].  When `loss` is set, the
+// soft-overlap term of every pair (i, j > i) with a controlled member is
+// added to *loss.  When `row` is set, margins / mask of row i are written.
+__device__ __forceinline__ void overlap_partial(const ObjLds &L, int N, int i0, int Ns, int U, int P, float *red,
+                                                float *loss, float *row_margin, uint8_t *row_mask)
+{
+    const int tid = threadIdx.x;
+    const int il = tid % U, part = tid / U;
+    if (part >= P)
+        return;
+    const int i = i0 + il;
+    float mmax = kNoValue;
+    if (il < Ns) {
+        const bool vi = L.valid[i];
+        const Box bi = lds_box(L, i);
+        for (int j = part; j < N; j += P) {
+            float m = kNoValue;
+            if (vi && j != i && L.valid[j]) {
+                const Box bj = lds_box(L, j);
+                m = i < j ? sat_margin(bi, bj) : sat_margin(bj, bi);
+                if (loss && j > i && (L.ctrl[i] || L.ctrl[j]))
+                    *loss += sigmoidf(m * (1.0f / kSoftScale));
+            }
+            if (row_margin)
+                row_margin[(long)il * N + j] = m;
+            if (row_mask)
+                row_mask[(long)il * N + j] = (uint8_t)(m > 0.f);
+            mmax = fmaxf(mmax, m);
+        }
+    }
+    red[part * U + il] = mmax;
+}
+
+// Off-road scan of the 4*Ns corners of slice objects i0.. against the
+// scenario's compacted edges, followed by the rescan that recovers the
+// lowest-index nearest point and the signed side of every corner.
+// Waves: w = tid / 64, corner wave cw = w % CW (256 corner slots each),
+// edge split g = w / CW.  Leaves sk[slot] and nidx[slot] (scenario-local
+// point index or -1) for slot < 4*Ns.  Contains two block barriers.
+__device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float2 *__restrict__ exy,
+                             const float2 *__restrict__ edir, const int32_t *__restrict__ eidx, int nch, int G,
+                             int CW, float *sbest, int *schunk, float *sk, int *nidx)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+    const int cw = w % CW, g = w / CW;
+    const int nslots = 4 * Ns;
+    const int SL = 256 * CW;
+    const int base = cw * 256;
+    const int avail = nslots - base;
+    const int Reff = avail <= 0 ? 0 : min(4, (avail + 63) >> 6);
+    const int cps = (nch + G - 1) / G;
+    const int c0 = min(nch, g * cps), c1 = min(nch, c0 + cps);
+    float cx[4], cy[4], best[4];
+    int bch[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int slot = base + lane + 64 * r;
+        slot = min(slot, max(nslots - 1, 0));
+        const int o = i0 + (slot >> 2);
+        box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, cx[r], cy[r]);
+        best[r] = __builtin_inff();
+        bch[r] = -1;
+    }
+    const float *ep = (const float *)exy;
+    if (Reff == 4) {
+        scan_edges<4>(ep, c0, c1, cx, cy, best, bch);
+    } else if (Reff == 3) {
+        float x3[3] = {cx[0], cx[1], cx[2]}, y3[3] = {cy[0], cy[1], cy[2]}, b3[3] = {best[0], best[1], best[2]};
+        int h3[3] = {bch[0], bch[1], bch[2]};
+        scan_edges<3>(ep, c0, c1, x3, y3, b3, h3);
+        for (int r = 0; r < 3; ++r) { best[r] = b3[r]; bch[r] = h3[r]; }
+    } else if (Reff == 2) {
+        float x2[2] = {cx[0], cx[1]}, y2[2] = {cy[0], cy[1]}, b2[2] = {best[0], best[1]};
+        int h2[2] = {bch[0], bch[1]};
+        scan_edges<2>(ep, c0, c1, x2, y2, b2, h2);
+        for (int r = 0; r < 2; ++r) { best[r] = b2[r]; bch[r] = h2[r]; }
+    } else if (Reff == 1) {
+        float x1[1] = {cx[0]}, y1[1] = {cy[0]}, b1[1] = {best[0]};
+        int h1[1] = {bch[0]};
+        scan_edges<1>(ep, c0, c1, x1, y1, b1, h1);
+        best[0] = b1[0];
+        bch[0] = h1[0];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int slot = base + lane + 64 * r;
+        if (r < Reff && slot < nslots) {
+            sbest[g * SL + slot] = best[r];
+            schunk[g * SL + slot] = bch[r];
+        }
+    }
+    __syncthreads();
+    for (int slot = tid; slot < nslots; slot += blockDim.x) {
+        float b = __builtin_inff();
+        int bc = -1;
+        for (int h = 0; h < G; ++h) {
+            const float v = sbest[h * SL + slot];
+            if (v < b) {
+                b = v;
+                bc = schunk[h * SL + slot];
+            }
+        }
+        const int o = i0 + (slot >> 2);
+        float s_val = kNoValue;
+        int near = -1;
+        if (bc >= 0 && L.valid[o]) {
+            float x, y;
+            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+            const int j = rescan_chunk(exy, bc, x, y, b);
+            const float2 q = exy[j], d = edir[j];
+            s_val = -__builtin_fmaf(d.x, y - q.y, -(d.y * (x - q.x)));
+            near = eidx[j];
+        }
+        sk[slot] = s_val;
+        nidx[slot] = near;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void load_object(ObjLds &L, int i, const wm_state &st, long g)
+{
+    L.x[i] = st.x[g];
+    L.y[i] = st.y[g];
+    L.yaw[i] = st.yaw[g];
+    L.vx[i] = st.vx[g];
+    L.vy[i] = st.vy[g];
+    L.len[i] = st.length[g];
+    L.wid[i] = st.width[g];
+    L.valid[i] = st.valid[g];
+    float s, c;
+    sincosf(L.yaw[i], &s, &c);
+    L.c[i] = c;
+    L.s[i] = s;
+}
+
+__device__ __forceinline__ void store_object(const ObjLds &L, int i, const wm_state &st, long g)
+{
+    st.x[g] = L.x[i];
+    st.y[g] = L.y[i];
+    st.yaw[g] = L.yaw[i];
+    st.vx[g] = L.vx[i];
+    st.vy[g] = L.vy[i];
+    st.length[g] = L.len[i];
+    st.width[g] = L.wid[i];
+    st.valid[g] = L.valid[i];
+}
+
+// Carve the LDS object arrays for up to maxN objects out of `p`; returns the
+// first byte after them.
+__device__ __forceinline__ unsigned char *carve_objects(unsigned char *p, int maxN, ObjLds &L)
+{
+    float *f = (float *)p;
+    L.x = f;
+    L.y = f + maxN;
+    L.yaw = f + 2 * maxN;
+    L.vx = f + 3 * maxN;
+    L.vy = f + 4 * maxN;
+    L.len = f + 5 * maxN;
+    L.wid = f + 6 * maxN;
+    L.c = f + 7 * maxN;
+    L.s = f + 8 * maxN;
+    uint8_t *b = (uint8_t *)(f + 9 * maxN);
+    L.valid = b;
+    L.ctrl = b + maxN;
+    return p + align_up((size_t)maxN * 38, 16);
+}
+
+// ---------------------------------------------------------------------------
+// Plain kernels (one launch per operation and step).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dynamics(StepArgs A)
+{
+    const int s = blockIdx.x;
+    const int o0 = A.obj_off[s], o1 = A.obj_off[s + 1];
+    for (int g = o0 + (int)threadIdx.x; g < o1; g += blockDim.x) {
+        const bool ctrl = A.act.controlled[g];
+        float x, y, yaw, vx, vy, len, wid;
+        uint8_t valid;
+        if (!ctrl) {
+            x = A.log_next.x[g]; y = A.log_next.y[g]; yaw = A.log_next.yaw[g];
+            vx = A.log_next.vx[g]; vy = A.log_next.vy[g]; len = A.log_next.length[g];
+            wid = A.log_next.width[g]; valid = A.log_next.valid[g];
+        } else {
+            x = A.cur.x[g]; y = A.cur.y[g]; yaw = A.cur.yaw[g]; vx = A.cur.vx[g]; vy = A.cur.vy[g];
+            len = A.cur.length[g]; wid = A.cur.width[g]; valid = A.cur.valid[g];
+            if (valid)
+                bicycle_forward(x, y, yaw, vx, vy, A.act.accel[g], A.act.curvature[g], A.dt);
+        }
+        A.next.x[g] = x; A.next.y[g] = y; A.next.yaw[g] = yaw; A.next.vx[g] = vx; A.next.vy[g] = vy;
+        A.next.length[g] = len; A.next.width[g] = wid; A.next.valid[g] = valid;
+        if (A.log_div) {
+            float d = 0.f;
+            if (valid && A.log_next.valid[g]) {
+                const float dx = x - A.log_next.x[g], dy = y - A.log_next.y[g];
+                d = sqrtf(__builtin_fmaf(dy, dy, dx * dx));
+            }
+            A.log_div[g] = d;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_inverse(int n, wm_state cur, wm_state nxt, float dt, float *__restrict__ accel,
+                                                 float *__restrict__ curv, uint8_t *__restrict__ vout)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n)
+        return;
+    const bool ok = cur.valid[g] && nxt.valid[g];
+    float a = 0.f, k = 0.f;
+    if (ok) {
+        const float vx = cur.vx[g], vy = cur.vy[g], nvx = nxt.vx[g], nvy = nxt.vy[g];
+        const float v = sqrtf(__builtin_fmaf(vy, vy, vx * vx));
+        const float nv = sqrtf(__builtin_fmaf(nvy, nvy, nvx * nvx));
+        a = (nv - v) / dt;
+        const float dist = __builtin_fmaf(v, dt, 0.5f * a * dt * dt);
+        const float heading = atan2f(nvy, nvx);
+        k = fabsf(dist) < 1e-6f ? 0.f : wrap_angle(heading - cur.yaw[g]) / dist;
+    }
+    accel[g] = a;
+    curv[g] = k;
+    if (vout)
+        vout[g] = (uint8_t)ok;
+}
+
+// Plain collision metric: block (scenario s, slice blockIdx.y) of U objects.
+__global__ __launch_bounds__(256) void k_overlap(OverlapArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    ObjLds L;
+    float *red = (float *)carve_objects(smem, A.maxN, L);
+    const int s = blockIdx.x;
+    const int o0 = A.obj_off[s], N = A.obj_off[s + 1] - o0;
+    const int i0 = blockIdx.y * A.U;
+    if (i0 >= N)
+        return;
+    const int Ns = min(A.U, N - i0);
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        load_object(L, i, A.st, o0 + i);
+    __syncthreads();
+    const int P = blockDim.x / A.U;
+    float *rm = A.margin ? A.margin + A.pair_off[s] + (long)i0 * N : nullptr;
+    uint8_t *rk = A.mask ? A.mask + A.pair_off[s] + (long)i0 * N : nullptr;
+    overlap_partial(L, N, i0, Ns, A.U, P, red, nullptr, rm, rk);
+    __syncthreads();
+    for (int il = threadIdx.x; il < Ns; il += blockDim.x) {
+        float m = kNoValue;
+        for (int p = 0; p < P; ++p)
+            m = fmaxf(m, red[p * A.U + il]);
+        const long g = o0 + i0 + il;
+        if (A.collision)
+            A.collision[g] = (uint8_t)(m > 0.f);
+        if (A.max_margin)
+            A.max_margin[g] = m;
+    }
+}
+
+// Plain off-road metric: block (scenario s, slice blockIdx.y) of 64*CW objects.
+__global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    ObjLds L;
+    unsigned char *p = carve_objects(smem, 64 * A.CW, L);
+    const int SL = 256 * A.CW;
+    float *sbest = (float *)p;
+    int *schunk = (int *)(sbest + A.G * SL);
+    float *sk = (float *)(schunk + A.G * SL);
+    int *nidx = (int *)(sk + SL);
+    const int s = blockIdx.x;
+    const int o0 = __builtin_amdgcn_readfirstlane(A.obj_off[s]);
+    const int N = __builtin_amdgcn_readfirstlane(A.obj_off[s + 1]) - o0;
+    const int U = 64 * A.CW;
+    const int i0 = blockIdx.y * U;
+    if (i0 >= N)
+        return;
+    const int Ns = min(U, N - i0);
+    for (int i = threadIdx.x; i < Ns; i += blockDim.x)
+        load_object(L, i, A.st, o0 + i0 + i);
+    __syncthreads();
+    const long eb = (long)__builtin_amdgcn_readfirstlane(A.rg_off[s]) + (long)s * kChunk;
+    const int nch = (__builtin_amdgcn_readfirstlane(A.ecount[s]) + kChunk - 1) / kChunk;
+    offroad_unit(L, 0, Ns, A.exy + eb, A.edir + eb, A.eidx + eb, nch, A.G, A.CW, sbest, schunk, sk, nidx);
+    for (int il = threadIdx.x; il < Ns; il += blockDim.x) {
+        float m = kNoValue;
+        for (int k = 0; k < 4; ++k)
+            m = fmaxf(m, sk[4 * il + k]);
+        const long g = o0 + i0 + il;
+        if (A.offroad)
+            A.offroad[g] = (uint8_t)(m > 0.f);
+        if (A.margin)
+            A.margin[g] = m;
+        if (A.nearest)
+            for (int k = 0; k < 4; ++k)
+                A.nearest[4 * g + k] = nidx[4 * il + k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent fused rollout.  Each work-group repeatedly takes the next unit
+// (scenario s, slice) from the queue and runs all T steps for it: dynamics of
+// all N_s objects (needed by the slice's pairs), then for the slice objects
+// the overlap, off-road, log divergence, loss terms, outputs and checkpoints.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_rollout(RollArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    ObjLds L;
+    unsigned char *p = carve_objects(smem, A.maxN, L);
+    const int U = 64 * A.CW;
+    const int SL = 256 * A.CW;
+    const int nthr = blockDim.x;
+    const int P = nthr / U;
+    float *sbest = (float *)p;
+    int *schunk = (int *)(sbest + A.G * SL);
+    float *sk = (float *)(schunk + A.G * SL);
+    int *nidx = (int *)(sk + SL);
+    float *red = (float *)(nidx + SL);
+    float *wsum = red + nthr;
+    __shared__ int s_unit;
+    const int tid = threadIdx.x;
+    const long n = A.n;
+    for (;;) {
+        if (tid == 0)
+            s_unit = atomicAdd(A.counter, 1);
+        __syncthreads();
+        // every value that selects road-edge addresses is made provably
+        // wave-uniform, so the scan's edge loads become scalar loads
+        const int q = __builtin_amdgcn_readfirstlane(s_unit);
+        if (q >= __builtin_amdgcn_readfirstlane(A.counter[1]))
+            break;
+        const int2 un = A.units[q];
+        const int s = __builtin_amdgcn_readfirstlane(un.x), slice = __builtin_amdgcn_readfirstlane(un.y);
+        const int o0 = __builtin_amdgcn_readfirstlane(A.obj_off[s]);
+        const int N = __builtin_amdgcn_readfirstlane(A.obj_off[s + 1]) - o0;
+        const int i0 = slice * U, Ns = min(U, N - i0);
+        const long eb = A.has_rg ? (long)__builtin_amdgcn_readfirstlane(A.rg_off[s]) + (long)s * kChunk : 0;
+        const int nch = A.has_rg ? (__builtin_amdgcn_readfirstlane(A.ecount[s]) + kChunk - 1) / kChunk : 0;
+        for (int i = tid; i < N; i += nthr) {
+            load_object(L, i, A.init, o0 + i);
+            L.ctrl[i] = A.act.controlled[o0 + i];
+        }
+        if (A.has_ckpt)
+            for (int il = tid; il < Ns; il += nthr)
+                store_object(L, i0 + il, A.ckpt, o0 + i0 + il);
+        __syncthreads();
+        float my_loss = 0.f;
+        for (int t = 1; t <= A.T; ++t) {
+            const long row = (long)t * n, arow = (long)(t - 1) * n;
+            for (int i = tid; i < N; i += nthr) {
+                const long g = o0 + i;
+                if (!L.ctrl[i]) {
+                    load_object(L, i, A.log, row + g);
+                } else if (L.valid[i]) {
+                    float x = L.x[i], y = L.y[i], yaw = L.yaw[i], vx = L.vx[i], vy = L.vy[i];
+                    bicycle_forward(x, y, yaw, vx, vy, A.act.accel[arow + g], A.act.curvature[arow + g], A.dt);
+                    L.x[i] = x; L.y[i] = y; L.yaw[i] = yaw; L.vx[i] = vx; L.vy[i] = vy;
+                    float sn, cs;
+                    sincosf(yaw, &sn, &cs);
+                    L.c[i] = cs;
+                    L.s[i] = sn;
+                }
+            }
+            __syncthreads();
+            for (int il = tid; il < Ns; il += nthr) {
+                const int i = i0 + il;
+                const long g = o0 + i;
+                if (A.has_traj)
+                    store_object(L, i, A.traj, arow + g);
+                if (A.has_ckpt && t % A.ckpt_every == 0 && t < A.T)
+                    store_object(L, i, A.ckpt, (long)(t / A.ckpt_every) * n + g);
+                const bool both = L.valid[i] && A.log.valid[row + g];
+                const float dx = L.x[i] - A.log.x[row + g], dy = L.y[i] - A.log.y[row + g];
+                const float d2 = __builtin_fmaf(dy, dy, dx * dx);
+                if (A.met.log_div)
+                    A.met.log_div[arow + g] = both ? sqrtf(d2) : 0.f;
+                if (A.want_loss && both && L.ctrl[i])
+                    my_loss += d2;
+            }
+            overlap_partial(L, N, i0, Ns, U, P, red, A.want_loss ? &my_loss : nullptr, nullptr, nullptr);
+            if (A.has_rg) {
+                offroad_unit(L, i0, Ns, A.exy + eb, A.edir + eb, A.eidx + eb, nch, A.G, A.CW, sbest, schunk, sk,
+                             nidx);
+            } else {
+                __syncthreads();
+            }
+            for (int il = tid; il < Ns; il += nthr) {
+                float m = kNoValue;
+                for (int pp = 0; pp < P; ++pp)
+                    m = fmaxf(m, red[pp * U + il]);
+                const long g = arow + o0 + i0 + il;
+                if (A.met.collision)
+                    A.met.collision[g] = (uint8_t)(m > 0.f);
+                if (A.met.overlap_margin)
+                    A.met.overlap_margin[g] = m;
+                if (A.has_rg) {
+                    float r = kNoValue;
+                    for (int k = 0; k < 4; ++k)
+                        r = fmaxf(r, sk[4 * il + k]);
+                    if (A.met.offroad)
+                        A.met.offroad[g] = (uint8_t)(r > 0.f);
+                    if (A.met.offroad_margin)
+                        A.met.offroad_margin[g] = r;
+                }
+            }
+            __syncthreads();
+        }
+        if (A.want_loss) {
+            // deterministic block sum: wave reduction then fixed-order sum
+            float v = my_loss;
+            for (int off = 32; off > 0; off >>= 1)
+                v += __shfl_xor(v, off);
+            if ((tid & 63) == 0)
+                wsum[tid >> 6] = v;
+            __syncthreads();
+            if (tid == 0) {
+                float tot = 0.f;
+                for (int w = 0; w < nthr / 64; ++w)
+                    tot += wsum[w];
+                A.lossp[A.uoff[s] + slice] = tot;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_loss_reduce(int S, const int32_t *__restrict__ uoff, const float *__restrict__ lossp,
+                              float *__restrict__ loss)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S)
+        return;
+    float tot = 0.f;
+    for (int u = uoff[s]; u < uoff[s + 1]; ++u)
+        tot += lossp[u];
+    loss[s] = tot;
+}
+
+} // namespace wm
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+namespace wm {
+
+static size_t objects_lds(int maxN) { return align_up((size_t)maxN * 38, 16); }
+
+void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned char *ws, const WsLayout &L,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_compact_edges<256>, dim3(b.num_scenarios), dim3(256), 0, st, b.rg_off, rg,
+                       (float2 *)(ws + L.exy), (float2 *)(ws + L.edir), (int32_t *)(ws + L.eidx),
+                       (int32_t *)(ws + L.ecount));
+}
+
+void launch_build_units(const wm_batch &b, int U, const int32_t *ecount, unsigned char *ws, const WsLayout &L,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_build_units, dim3(1), dim3(1024), 0, st, b.obj_off, ecount, b.num_scenarios, U,
+                       (int32_t *)(ws + L.uoff), (int2 *)(ws + L.units), (int32_t *)(ws + L.counter));
+}
+
+void launch_dynamics(const wm_batch &b, const StepArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dynamics, dim3(b.num_scenarios), dim3(128), 0, st, a);
+}
+
+void launch_inverse(int n, const wm_state &cur, const wm_state &nxt, float dt, float *accel, float *curv,
+                    uint8_t *vout, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_inverse, dim3((n + 255) / 256), dim3(256), 0, st, n, cur, nxt, dt, accel, curv, vout);
+}
+
+void launch_overlap(const wm_batch &b, const OverlapArgs &a, hipStream_t st)
+{
+    const size_t lds = objects_lds(a.maxN) + 256 * sizeof(float);
+    const int slices = (b.max_objects + a.U - 1) / a.U;
+    if (lds > 65536)
+        hipFuncSetAttribute((const void *)k_overlap, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_overlap, dim3(b.num_scenarios, slices), dim3(256), lds, st, a);
+}
+
+static size_t offroad_scratch(int G, int CW) { return (size_t)G * 256 * CW * 8 + (size_t)256 * CW * 8; }
+
+void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
+{
+    const size_t lds = objects_lds(64 * a.CW) + offroad_scratch(a.G, a.CW);
+    const int slices = (b.max_objects + 64 * a.CW - 1) / (64 * a.CW);
+    if (lds > 65536)
+        hipFuncSetAttribute((const void *)k_offroad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_offroad, dim3(b.num_scenarios, slices), dim3(64 * a.CW * a.G), lds, st, a);
+}
+
+size_t rollout_lds_bytes(int maxN, int G, int CW)
+{
+    const int nthr = 64 * CW * G;
+    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4;
+}
+
+int rollout_grid(int G, int CW, int maxN, int n_units_bound)
+{
+    const int nthr = 64 * CW * G;
+    const size_t lds = rollout_lds_bytes(maxN, G, CW);
+    if (lds > 65536)
+        hipFuncSetAttribute((const void *)k_rollout, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rollout, nthr, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1)
+        cus = 1;
+    const long grid = (long)per_cu * cus;
+    return (int)(grid < n_units_bound ? grid : (n_units_bound < 1 ? 1 : n_units_bound));
+}
+
+void launch_rollout(const RollArgs &a, int grid, hipStream_t st)
+{
+    const size_t lds = rollout_lds_bytes(a.maxN, a.G, a.CW);
+    hipLaunchKernelGGL(k_rollout, dim3(grid), dim3(64 * a.CW * a.G), lds, st, a);
+}
+
+void launch_loss_reduce(int S, const int32_t *uoff, const float *lossp, float *loss, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_loss_reduce, dim3((S + 255) / 256), dim3(256), 0, st, S, uoff, lossp, loss);
+}
+
+} // namespace wm

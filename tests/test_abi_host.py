@@ -1,0 +1,167 @@
+"""The C-ABI library loads on a machine without a GPU, exports every function
+that include/wm.h declares, and rejects bad host-visible arguments before
+touching the device (no call here reaches a launch)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2310_08710_amd import wm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wm.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(wm.LIB_PATH), reason="libwm.so not built")
+
+FAKE = 0x100000  # never dereferenced: every call below fails validation first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wm_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 11
+    lib = wm.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _batch(S=2, n=10, P=100, max_obj=6, max_rg=60):
+    return wm.CBatch(S, n, P, max_obj, max_rg, FAKE, FAKE)
+
+
+def _state(null_field=None):
+    vals = [FAKE] * 8
+    if null_field is not None:
+        vals[null_field] = None
+    return wm.CState(*vals)
+
+
+def _rg():
+    return wm.CRoadgraph(*([FAKE] * 6))
+
+
+def _act():
+    return wm.CAction(FAKE, FAKE, FAKE)
+
+
+def _msg():
+    return wm.lib().wm_last_error_message().decode()
+
+
+def step(batch=None, cur=None, act=None, log=None, rg=None, dt=0.1, nxt=None, m=None, ws=None, ws_bytes=0):
+    b = batch if batch is not None else _batch()
+    cur = cur if cur is not None else _state()
+    nxt = nxt if nxt is not None else wm.CState(*([FAKE + 64] * 8))
+    return wm.lib().wm_step(C.byref(b), C.byref(cur), C.byref(act if act is not None else _act()),
+                            C.byref(log if log is not None else _state()), C.byref(rg) if rg is not None else None,
+                            dt, C.byref(nxt), C.byref(m) if m is not None else None, ws, ws_bytes, None)
+
+
+def test_error_strings():
+    for code in range(7):
+        assert wm.error_string(code)
+    assert "unknown" in wm.error_string(99)
+
+
+def test_workspace_bytes_pure_host():
+    b = _batch()
+    n0 = wm.lib().wm_workspace_bytes(C.byref(b), 0, 0)
+    n1 = wm.lib().wm_workspace_bytes(C.byref(b), 80, 10)
+    assert 0 < n0 < n1
+    bad = _batch(S=0)
+    assert wm.lib().wm_workspace_bytes(C.byref(bad), 0, 0) == 0
+
+
+def test_step_validation():
+    assert wm.lib().wm_step(None, None, None, None, None, 0.1, None, None, None, 0, None) == wm.WM_ERR_NULL
+    assert step(batch=_batch(S=0)) == wm.WM_ERR_RANGE
+    assert step(batch=_batch(max_obj=20)) == wm.WM_ERR_SHAPE                  # max > total
+    assert step(batch=wm.CBatch(1, 2000, 10, 1100, 10, FAKE, FAKE)) == wm.WM_ERR_UNSUPPORTED
+    assert step(batch=wm.CBatch(1, 10, 10, 10, 10, None, FAKE)) == wm.WM_ERR_NULL
+    assert step(cur=_state(null_field=3)) == wm.WM_ERR_NULL
+    assert "cur" in _msg()
+    assert step(act=wm.CAction(FAKE, None, FAKE)) == wm.WM_ERR_NULL
+    for dt in (0.0, -0.1, float("nan"), float("inf")):
+        assert step(dt=dt) == wm.WM_ERR_RANGE
+    assert step(nxt=_state()) == wm.WM_ERR_RANGE                              # next aliases cur
+    m = wm.CMetrics(None, FAKE, None, None, None)
+    assert step(rg=_rg(), m=m) == wm.WM_ERR_WORKSPACE                          # offroad needs workspace
+    assert "workspace" in _msg()
+    assert step(rg=_rg(), m=m, ws=FAKE, ws_bytes=16) == wm.WM_ERR_WORKSPACE
+    assert step(rg=wm.CRoadgraph(FAKE, FAKE, None, FAKE, FAKE, FAKE), m=m) == wm.WM_ERR_NULL
+
+
+def test_offroad_and_tuning_validation():
+    L = wm.lib()
+    b, s, r = _batch(), _state(), _rg()
+    need = L.wm_workspace_bytes(C.byref(b), 0, 0)
+    for U, G in ((32, 4), (64, 3), (256, 8), (128, 32)):
+        t = wm.CTuning(U, G)
+        rc = L.wm_offroad(C.byref(b), C.byref(s), C.byref(r), FAKE, FAKE, None, C.byref(t), FAKE, need, None)
+        assert rc == wm.WM_ERR_RANGE, (U, G)
+    rc = L.wm_offroad(C.byref(b), C.byref(s), None, FAKE, FAKE, None, None, FAKE, need, None)
+    assert rc == wm.WM_ERR_NULL
+    rc = L.wm_offroad(C.byref(b), C.byref(s), C.byref(r), FAKE, FAKE, None, None, FAKE, need - 1, None)
+    assert rc == wm.WM_ERR_WORKSPACE
+
+
+def test_observe_validation():
+    L = wm.lib()
+    b, s, r = _batch(), _state(), _rg()
+    assert L.wm_observe(C.byref(b), C.byref(s), C.byref(r), FAKE, 0, 10, FAKE, None, None, None) == wm.WM_ERR_RANGE
+    assert L.wm_observe(C.byref(b), C.byref(s), C.byref(r), FAKE, 8, 0, FAKE, None, None, None) == wm.WM_ERR_RANGE
+    assert L.wm_observe(C.byref(b), C.byref(s), C.byref(r), FAKE, 8, 2000, FAKE, None, None,
+                        None) == wm.WM_ERR_UNSUPPORTED
+    big = wm.CBatch(1, 10, 40000, 10, 40000, FAKE, FAKE)
+    assert L.wm_observe(C.byref(big), C.byref(s), C.byref(r), FAKE, 8, 10, FAKE, None, None,
+                        None) == wm.WM_ERR_UNSUPPORTED
+    assert L.wm_observe(C.byref(b), C.byref(s), C.byref(r), None, 8, 10, FAKE, None, None, None) == wm.WM_ERR_NULL
+
+
+def test_rollout_validation():
+    L = wm.lib()
+    b, s, a, r = _batch(), _state(), _act(), _rg()
+    need = L.wm_workspace_bytes(C.byref(b), 80, 10)
+
+    def roll(T=80, dt=0.1, K=10, ck=None, ws_bytes=need, tune=None, act=a):
+        return L.wm_rollout(C.byref(b), C.byref(s), C.byref(act), C.byref(s), C.byref(r), T, dt, K,
+                            C.byref(ck) if ck is not None else None, None, None, None,
+                            C.byref(tune) if tune is not None else None, FAKE, ws_bytes, None)
+
+    assert roll(T=0) == wm.WM_ERR_RANGE
+    assert roll(dt=0.0) == wm.WM_ERR_RANGE
+    assert roll(K=-1) == wm.WM_ERR_RANGE
+    assert roll(K=0, ck=_state()) == wm.WM_ERR_RANGE
+    assert roll(ck=_state(null_field=7)) == wm.WM_ERR_NULL
+    assert roll(ws_bytes=need - 1) == wm.WM_ERR_WORKSPACE
+    assert roll(tune=wm.CTuning(64, 5)) == wm.WM_ERR_RANGE
+    assert roll(act=wm.CAction(None, FAKE, FAKE)) == wm.WM_ERR_NULL
+    bb = wm.CBatch(1, 30000000, 10, 1000, 10, FAKE, FAKE)
+    assert L.wm_rollout(C.byref(bb), C.byref(s), C.byref(a), C.byref(s), None, 80, 0.1, 0, None, None, None, None,
+                        None, FAKE, 1 << 40, None) == wm.WM_ERR_UNSUPPORTED
+
+    def back(K=10, dloss=FAKE, ga=FAKE, ws_bytes=need, ck=s):
+        return L.wm_rollout_backward(C.byref(b), C.byref(s), C.byref(a), C.byref(s), 80, 0.1, K,
+                                     C.byref(ck) if ck is not None else None, dloss, ga, FAKE, FAKE, ws_bytes, None)
+
+    assert back(K=0) == wm.WM_ERR_RANGE
+    assert back(dloss=None) == wm.WM_ERR_NULL
+    assert back(ga=None) == wm.WM_ERR_NULL
+    assert back(ck=None) == wm.WM_ERR_NULL
+    assert back(ws_bytes=0) == wm.WM_ERR_WORKSPACE
+
+
+def test_inverse_and_overlap_validation():
+    L = wm.lib()
+    b, s = _batch(), _state()
+    assert L.wm_inverse_action(C.byref(b), C.byref(s), C.byref(s), 0.1, None, FAKE, None, None) == wm.WM_ERR_NULL
+    assert L.wm_inverse_action(C.byref(b), C.byref(s), C.byref(s), -1.0, FAKE, FAKE, None, None) == wm.WM_ERR_RANGE
+    assert L.wm_overlap(C.byref(b), C.byref(s), None, FAKE, None, None, None, None) == wm.WM_ERR_NULL
+    # nothing requested: a no-op that never launches
+    assert L.wm_overlap(C.byref(b), C.byref(s), None, None, None, None, None, None) == wm.WM_OK

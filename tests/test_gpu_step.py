@@ -1,0 +1,201 @@
+"""GPU parity of the single-step entry points against the FP64 oracle on the
+same float32 inputs: dynamics (App. A.1), inverse kinematics, collision and
+off-road metrics (Sec. 3.4), through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import (ATOL, BAND, assert_state_close, compare_collision, compare_offroad, device, f64, within)
+from paper_2310_08710_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(kind):
+    if kind == "config0":
+        return synth.make_scene(0)
+    if kind == "ragged":
+        return synth.make_scene(2, scenarios=7, objects=(1, 70), rg_points=(24, 4000), steps=4,
+                                invalid_frac=0.1, rg_invalid_frac=0.05, object_box=40, on_road_frac=0.5)
+    if kind == "dense":
+        return synth.make_scene(1, scenarios=3, objects=(100, 130), rg_points=(3000, 6000), steps=3,
+                                object_box=25, on_road_frac=0.7, invalid_frac=0.05)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["config0", "ragged", "dense"])
+def test_step_dynamics_and_playback(kind):
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _scene(kind)
+    ds = wm.upload(sc, dev)
+    n = sc.total_objects
+    ctrl = sc.controlled.copy()
+    ctrl[::4] = 0                                   # some objects replay the log
+    act = wm.Action(ds.act_seq.accel[0].contiguous(), ds.act_seq.curvature[0].contiguous(),
+                    torch.from_numpy(ctrl).to(dev))
+    nxt = wm.State.empty(n, dev)
+    wm.step(ds.batch, ds.init, act, ds.log_seq.row(1), None, sc.dt, nxt)
+    torch.cuda.synchronize()
+    g = nxt.numpy()
+    lw = sc.log_window()
+    ref = oracle.bicycle_forward(f64({k: v[0] for k, v in lw.items()}), sc.accel[0], sc.curvature[0], ctrl,
+                                 f64({k: v[1] for k, v in lw.items()}), sc.dt)
+    assert_state_close(g, ref, kind)
+    # replayed objects are the log bit for bit
+    for f in synth.STATE_FIELDS:
+        np.testing.assert_array_equal(g[f][ctrl == 0], lw[f][1][ctrl == 0])
+    # frozen objects (controlled, invalid) are unchanged bit for bit
+    frozen = (ctrl == 1) & (lw["valid"][0] == 0)
+    for f in synth.STATE_FIELDS:
+        np.testing.assert_array_equal(g[f][frozen], lw[f][0][frozen])
+
+
+@pytest.mark.parametrize("kind", ["config0", "ragged"])
+def test_inverse_action(kind):
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _scene(kind)
+    ds = wm.upload(sc, dev)
+    n = sc.total_objects
+    a = torch.empty(n, device=dev)
+    k = torch.empty(n, device=dev)
+    v = torch.empty(n, dtype=torch.uint8, device=dev)
+    wm.inverse_action(ds.batch, ds.log_seq.row(0), ds.log_seq.row(1), sc.dt, a, k, v)
+    torch.cuda.synchronize()
+    lw = sc.log_window()
+    ra, rk, rv = oracle.bicycle_inverse(f64({q: w[0] for q, w in lw.items()}), f64({q: w[1] for q, w in lw.items()}),
+                                        sc.dt)
+    np.testing.assert_array_equal(v.cpu().numpy(), rv)
+    # a = (|v'| - |v|)/dt: each speed carries ~1 ulp (speeds < 64 m/s: ulp <= 7.6e-6),
+    # so |error| <= 2 * 7.6e-6 / dt on top of the relative tolerance
+    a_tol = 2 * 7.63e-6 / sc.dt
+    assert within(a.cpu().numpy(), ra, atol=a_tol).all()
+    # kappa = angle / distance with distance >= 0.5 m/s * dt: angle error of a
+    # few ulp of pi over 0.05 m
+    k_tol = 4 * 2.4e-7 / (0.5 * sc.dt)
+    assert within(k.cpu().numpy(), rk, atol=k_tol).all()
+
+
+@pytest.mark.parametrize("kind", ["config0", "ragged", "dense"])
+def test_overlap_metric_and_matrix(kind):
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _scene(kind)
+    ds = wm.upload(sc, dev)
+    n = sc.total_objects
+    counts = np.diff(sc.obj_off).astype(np.int64)
+    pair_off = np.zeros(len(counts) + 1, np.int64)
+    pair_off[1:] = np.cumsum(counts ** 2)
+    po = torch.from_numpy(pair_off).to(dev)
+    col = torch.empty(n, dtype=torch.uint8, device=dev)
+    mm = torch.empty(n, device=dev)
+    M = torch.empty(max(int(pair_off[-1]), 1), device=dev)
+    K = torch.empty(max(int(pair_off[-1]), 1), dtype=torch.uint8, device=dev)
+    wm.overlap(ds.batch, ds.init, col, mm, po, M, K)
+    torch.cuda.synchronize()
+    st = f64(sc.state_at(synth.T0))
+    o_col, o_mm, blocks = oracle.overlap(sc.obj_off, st, matrix=True)
+    ties = compare_collision(col.cpu().numpy(), mm.cpu().numpy(), o_col, o_mm, kind)
+    Mg, Kg = M.cpu().numpy(), K.cpu().numpy()
+    for s, N in enumerate(counts):
+        B = Mg[pair_off[s]:pair_off[s] + N * N].reshape(N, N)
+        np.testing.assert_array_equal(B, B.T)                       # exactly symmetric
+        assert within(B, blocks[s]).all()
+        tie = np.abs(blocks[s]) < BAND
+        np.testing.assert_array_equal(Kg[pair_off[s]:pair_off[s] + N * N].reshape(N, N)[~tie],
+                                      (blocks[s] > 0)[~tie].astype(np.uint8))
+    if kind == "dense":
+        assert o_col.sum() > 10 and ties < 3
+
+
+@pytest.mark.parametrize("kind", ["config0", "ragged", "dense"])
+@pytest.mark.parametrize("tune", [None, (64, 1), (64, 4), (128, 2), (256, 4)])
+def test_offroad_metric(kind, tune):
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _scene(kind)
+    ds = wm.upload(sc, dev)
+    n = sc.total_objects
+    ws = ds.batch.workspace()
+    off = torch.empty(n, dtype=torch.uint8, device=dev)
+    mg = torch.empty(n, device=dev)
+    near = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    wm.offroad(ds.batch, ds.init, ds.rg, ws, off, mg, near, tune=tune)
+    torch.cuda.synchronize()
+    ref = oracle.offroad(sc.obj_off, sc.rg_off, f64(sc.state_at(synth.T0)), f64(sc.rg), band=BAND)
+    ties = compare_offroad(off.cpu().numpy(), mg.cpu().numpy(), ref, kind)
+    amb = ref["ambiguous"].astype(bool)
+    g_near = near.cpu().numpy()
+    np.testing.assert_array_equal(g_near[~amb], ref["nearest"][~amb])
+    assert ties <= max(2, n // 50)
+    if kind == "dense":
+        assert 0 < ref["offroad"].mean() < 1
+
+
+def test_step_with_metrics_matches_separate_calls():
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _scene("dense")
+    ds = wm.upload(sc, dev)
+    n = sc.total_objects
+    act = wm.Action(ds.act_seq.accel[0].contiguous(), ds.act_seq.curvature[0].contiguous(), ds.act_seq.controlled)
+    nxt = wm.State.empty(n, dev)
+    m = wm.Metrics.empty(n, dev)
+    ws = ds.batch.workspace()
+    wm.step(ds.batch, ds.init, act, ds.log_seq.row(1), ds.rg, sc.dt, nxt, m, ws)
+    col = torch.empty(n, dtype=torch.uint8, device=dev)
+    mm = torch.empty(n, device=dev)
+    off = torch.empty(n, dtype=torch.uint8, device=dev)
+    om = torch.empty(n, device=dev)
+    wm.overlap(ds.batch, nxt, col, mm)
+    wm.offroad(ds.batch, nxt, ds.rg, ws, off, om)
+    torch.cuda.synchronize()
+    assert torch.equal(col, m.collision) and torch.equal(mm, m.overlap_margin)
+    assert torch.equal(off, m.offroad) and torch.equal(om, m.offroad_margin)
+    # metrics of the successor state against the oracle (teacher-forced)
+    g = nxt.numpy()
+    o_col, o_mm, _ = oracle.overlap(sc.obj_off, f64(g))
+    compare_collision(m.collision.cpu().numpy(), m.overlap_margin.cpu().numpy(), o_col, o_mm, "step")
+    ref = oracle.offroad(sc.obj_off, sc.rg_off, f64(g), f64(sc.rg), band=BAND)
+    compare_offroad(m.offroad.cpu().numpy(), m.offroad_margin.cpu().numpy(), ref, "step")
+    lg = {k: v[1] for k, v in sc.log_window().items()}
+    assert within(m.log_div.cpu().numpy(), oracle.log_divergence(f64(g), f64(lg))).all()
+
+
+def test_offroad_exact_ties_and_empty_scenarios():
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    # scenario 0: the 3-4-5 tie of the oracle pin (corner FL = (2, 1) exactly);
+    # scenario 1: no road edge at all; scenario 2: no objects
+    pts = np.array([[5.0, 5.0], [-1.0, -3.0], [50.0, 50.0], [0.0, 0.0]], np.float64)
+    rg = {"x": pts[:, 0], "y": pts[:, 1], "dir_x": np.ones(4), "dir_y": np.zeros(4),
+          "type": np.array([1, 1, 1, 0], np.int8), "valid": np.ones(4, np.uint8)}
+    obj_off = np.array([0, 1, 2, 2], np.int32)
+    rg_off = np.array([0, 3, 4, 4], np.int32)
+    st = {"x": np.array([0.0, 3.0]), "y": np.array([0.0, 3.0]), "yaw": np.zeros(2), "vx": np.zeros(2),
+          "vy": np.zeros(2), "length": np.array([4.0, 4.0]), "width": np.array([2.0, 2.0]),
+          "valid": np.ones(2, np.uint8)}
+    batch = wm.Batch.from_offsets(obj_off, rg_off, dev)
+    S = wm.State.from_numpy(st, dev)
+    R = wm.Roadgraph.from_numpy(rg, dev)
+    ws = batch.workspace()
+    off = torch.empty(2, dtype=torch.uint8, device=dev)
+    mg = torch.empty(2, device=dev)
+    near = torch.empty((2, 4), dtype=torch.int32, device=dev)
+    wm.offroad(batch, S, R, ws, off, mg, near)
+    torch.cuda.synchronize()
+    ref = oracle.offroad(obj_off, rg_off, st, rg)
+    np.testing.assert_array_equal(near.cpu().numpy(), ref["nearest"])
+    assert near[0, 0].item() == 0                    # lower index wins the exact tie
+    np.testing.assert_array_equal(off.cpu().numpy(), ref["offroad"])
+    np.testing.assert_allclose(mg.cpu().numpy(), ref["margin"], rtol=0, atol=ATOL)
+    assert mg[1].item() == wm.NO_VALUE and off[1].item() == 0 and (near[1] == -1).all()

@@ -160,3 +160,29 @@ def test_straight_line_gradient_closed_form():
     np.testing.assert_allclose(ga[:, 0], expect, rtol=1e-10, atol=1e-12)
     exp_loss = ((x[1:] - log["x"][1:, 0]) ** 2 + (y[1:] - log["y"][1:, 0]) ** 2).sum()
     assert abs(loss[0] - exp_loss) < 1e-9
+
+
+def test_state_loss_closed_form():
+    # two controlled boxes side by side with a 0.05 m lateral overlap, one of
+    # them 5 m (3-4-5) from its logged position: loss = 25 + sigmoid(0.05 / 0.1)
+    yaw = 0.3
+    wx, wy = -math.sin(yaw), math.cos(yaw)
+    st = {"x": np.array([0.0, 1.9 * wx]), "y": np.array([0.0, 1.9 * wy]), "yaw": np.array([yaw, yaw]),
+          "vx": np.zeros(2), "vy": np.zeros(2), "length": np.array([4.5, 4.0]), "width": np.array([2.0, 1.9]),
+          "valid": np.ones(2, np.uint8)}
+    log = {k: v.copy() for k, v in st.items()}
+    log["x"][0] += 3.0
+    log["y"][0] -= 4.0
+    off = np.array([0, 2], np.int32)
+    L = oracle.state_loss(off, st, log, np.ones(2, np.uint8))
+    assert abs(L[0] - (25.0 + 1.0 / (1.0 + math.exp(-0.5)))) < 1e-12
+    # uncontrolled pair: no terms at all
+    assert oracle.state_loss(off, st, log, np.zeros(2, np.uint8))[0] == 0.0
+    # the rollout loss is the sum of the per-step state losses
+    sc = synth.make_scene(3, scenarios=2, objects=(10, 10), rg_points=(240, 240), steps=6, object_box=10)
+    init, lw = _f64(sc.state_at(synth.T0)), _f64(sc.log_window())
+    out = oracle.rollout(sc.obj_off, None, init, sc.accel, sc.curvature, sc.controlled, lw, None, 6, DT,
+                         metrics=False)
+    tot = sum(oracle.state_loss(sc.obj_off, {f: out["traj"][f][t] for f in out["traj"]},
+                                {f: lw[f][t + 1] for f in lw}, sc.controlled) for t in range(6))
+    np.testing.assert_allclose(out["loss"], tot, rtol=1e-12)
