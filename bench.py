@@ -1,0 +1,353 @@
+"""Benchmark of the simulator hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+
+Workload: 256 scenarios x 128 objects, 30,000 road points per scenario
+(about 20,000 road-edge points), an 80-step rollout at dt = 0.1 s (synthetic
+scenes shaped like the paper's runtime benchmark, Sec. 5.1 / App. A.3).  One
+timed step is one expert rollout (RolloutExpert in the paper's runtime
+table): expert actions from inverse kinematics on the logs, then the fused
+persistent rollout kernel with every metric (collision, off-road,
+displacement) at every step.  value = agent-steps/s = objects x 80 x K / time.
+
+Also reported on the same line: the dominant kernel against the FP32 roofline
+(HIP events around the persistent kernel), the FP64 CPU oracle on a bounded
+sample of the same workload, the plain per-step form (separate launches per
+operation, captured in a HIP graph), the differentiable rollout (forward +
+adjoint) and the observation (8 egos per scenario, k = 1000).
+Progress goes to stderr; stdout carries exactly one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12        # MI355X FP32 vector peak [FLOP/s] (published)
+PEAK_HBM = 8.0e12           # MI355X HBM3E [B/s] (published)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def edge_counts(scene):
+    is_edge = (scene.rg["type"] == 1) & (scene.rg["valid"] == 1)
+    c = np.concatenate([[0], np.cumsum(is_edge.astype(np.int64))])
+    return c[scene.rg_off[1:]] - c[scene.rg_off[:-1]]
+
+
+def rollout_ops(scene, T):
+    """Algorithmic FP32 operations of one fused rollout launch: per agent-step,
+    off-road 4 corners x E_s edge points x 6 ops, overlap 20 ops x (N_s - 1)
+    (40 ops per pair, each pair shared by two agents), dynamics and
+    displacement 35 ops."""
+    N = np.diff(scene.obj_off).astype(np.float64)
+    E = edge_counts(scene).astype(np.float64)
+    per_step = (N * (4.0 * E * 6.0 + 20.0 * np.maximum(N - 1, 0) + 35.0)).sum()
+    return per_step * T, float((4.0 * N * E).sum() * T)
+
+
+def recorded_traffic(tune):
+    """HBM-side bytes per k_rollout launch from the committed rocprofv3
+    counter runs, or None when the kernel sources or the tuning changed since."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_rollout_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2310_08710_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    if rec.get("sources_sha256") != h.hexdigest() or list(rec.get("tuning", [])) != list(tune or []):
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(scene, sample, threads):
+    """The FP64 oracle (as it stands) on the first `sample` scenarios of the
+    workload, one scenario per thread; agent-steps/s."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    lw = scene.log_window()
+    T = scene.steps
+
+    def one(s):
+        o0, o1 = int(scene.obj_off[s]), int(scene.obj_off[s + 1])
+        p0, p1 = int(scene.rg_off[s]), int(scene.rg_off[s + 1])
+        sub = {k: v[:, o0:o1] for k, v in lw.items()}
+        f64 = lambda d: {k: (v.astype(np.float64) if v.dtype == np.float32 else v) for k, v in d.items()}  # noqa
+        rg = f64({k: v[p0:p1] for k, v in scene.rg.items()})
+        oracle.rollout(np.array([0, o1 - o0], np.int32), np.array([0, p1 - p0], np.int32),
+                       f64({k: v[0] for k, v in sub.items()}), scene.accel[:, o0:o1], scene.curvature[:, o0:o1],
+                       scene.controlled[o0:o1], f64(sub), rg, T, scene.dt, metrics=True, want_loss=False)
+        return o1 - o0
+
+    oracle.lib()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        objs = sum(ex.map(one, range(sample)))
+    dt = time.perf_counter() - t0
+    return objs * T / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-extras", action="store_true", help="skip plain / fwd+bwd / observation")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune", type=str, default=None, help="unit_objects,edge_splits (skips the autotuner)")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="scenarios of the oracle sample")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device once (calibrates HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe * 262144, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB" % args.copy_probe)
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (scenarios are independent, "
+              "so N GPUs would each run their own share of the batch); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_08710_amd import synth, wm
+
+    dev = torch.device("cuda:0")
+    wm.lib()
+    t = time.perf_counter()
+    scene = synth.make_scene(1)
+    ds = wm.upload(scene, dev)
+    torch.cuda.synchronize()
+    S, n, T = scene.num_scenarios, scene.total_objects, scene.steps
+    log("scene: %d scenarios, %d objects, %d road points, T=%d (%.1fs)" % (S, n, scene.total_rg_points, T,
+                                                                          time.perf_counter() - t))
+
+    # expert actions for the whole window in one launch: rows 0..T-1 -> 1..T
+    inv_batch = wm.Batch(ds.batch.obj_off, ds.batch.rg_off, 1, T * n, ds.batch.total_rg_points, 0, 0)
+    lg = ds.log_seq
+    cur = wm.State(*[getattr(lg, f)[:T] for f in wm.STATE_FIELDS + ("valid",)])
+    nxt = wm.State(*[getattr(lg, f)[1:] for f in wm.STATE_FIELDS + ("valid",)])
+    ea = torch.empty((T, n), device=dev)
+    ek = torch.empty((T, n), device=dev)
+    expert = wm.Action(ea, ek, ds.act_seq.controlled)
+    traj = wm.State.empty((T, n), dev)
+    met = wm.Metrics.empty((T, n), dev)
+    ws = ds.batch.workspace(T, 10)
+
+    tune = None
+    if args.tune:
+        tune = tuple(int(v) for v in args.tune.split(","))
+    elif not args.no_autotune:
+        wm.inverse_action(inv_batch, cur, nxt, scene.dt, ea, ek)
+        tune = wm.autotune(ds.batch, ds.init, expert, ds.log_seq, ds.rg, T, scene.dt, ws)
+        log("autotuned (unit_objects, edge_splits) =", tune)
+
+    def step():
+        wm.inverse_action(inv_batch, cur, nxt, scene.dt, ea, ek)
+        wm.rollout(ds.batch, ds.init, expert, ds.log_seq, ds.rg, T, scene.dt, ws, traj=traj, metrics=met,
+                   tune=tune)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_ROLLOUT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = wm.profile_collect(wm.PROF_ROLLOUT)
+    wm.profile_enable(False)
+    valid_objs = int(scene.log["valid"][synth.T0].sum())
+    value = valid_objs * T * args.steps / wall
+    ms_per_step = 1e3 * wall / args.steps
+    kernel_ms = kms / max(launches, 1)
+    ops, pairs = rollout_ops(scene, T)
+    achieved = ops / (kernel_ms * 1e-3)
+    log("fused rollout: %.3f ms/step, kernel %.3f ms, %.3e agent-steps/s, %.1f TFLOP/s algorithmic" % (
+        ms_per_step, kernel_ms, value, achieved / 1e12))
+    assert torch.isfinite(met.offroad_margin).all() and torch.isfinite(traj.x).all()
+
+    out = {
+        "metric": "agent-steps/s (step+metrics)",
+        "value": value,
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "expert rollout of 256 scenarios x 128 objects, 30000 road points "
+                               "(~20000 road edges) per scenario, 80 steps, every metric every step",
+                   "scenarios": S, "objects_per_scenario": 128, "rg_points": 30000, "T": T,
+                   "tuning": list(tune) if tune else None},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": recorded_traffic(tune), "kernel": "k_rollout",
+                     "kernel_ms": kernel_ms, "ops_per_launch": ops, "corner_edge_pairs_per_launch": pairs},
+    }
+
+    if not args.no_extras:
+        extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune)
+
+    if not args.no_cpu:
+        try:
+            threads = len(os.sched_getaffinity(0))
+        except AttributeError:
+            threads = os.cpu_count() or 1
+        threads = max(1, min(threads, 16, args.cpu_sample))
+        rate, secs = cpu_baseline(scene, args.cpu_sample, threads)
+        out["cpu_baseline"] = {"value": rate, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
+                               "sample": "%d of the 256 scenarios, all 80 steps with every metric, FP64 C oracle, "
+                                         "one scenario per thread (%.1f s wall)" % (args.cpu_sample, secs)}
+        log("cpu oracle: %.3e agent-steps/s on %d threads (%.1f s)" % (rate, threads, secs))
+    print(json.dumps(out), flush=True)
+
+
+def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
+    import torch
+    from paper_2310_08710_amd import wm
+    S, n, T = scene.num_scenarios, scene.total_objects, scene.steps
+    reps = 3
+
+    # plain form: one launch per operation and step, replayed as a HIP graph
+    traj = wm.State.empty((T, n), dev)
+    met = wm.Metrics.empty((T, n), dev)
+    ws0 = ds.batch.workspace()
+    fields = ("collision", "offroad", "overlap_margin", "offroad_margin", "log_div")
+
+    def plain():
+        wm.inverse_action(inv_batch, cur, nxt, scene.dt, ea, ek)
+        c = ds.init
+        for t in range(1, T + 1):
+            act = wm.Action(ea[t - 1], ek[t - 1], ds.act_seq.controlled)
+            m = wm.Metrics(*[getattr(met, f)[t - 1] for f in fields])
+            wm.step(ds.batch, c, act, ds.log_seq.row(t), ds.rg, scene.dt, traj.row(t - 1), m, ws0)
+            c = traj.row(t - 1)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plain()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plain()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    pms = 1e3 * (time.perf_counter() - t0) / reps
+    fused_ms = out["ms_per_step"]
+    out["plain"] = {"value": n * T / (pms * 1e-3), "unit": "agent-steps/s", "ms_per_rollout": pms,
+                    "form": "per-step launches (dynamics, overlap, edge compaction, off-road) in one HIP graph",
+                    "fused_speedup": pms / fused_ms}
+    log("plain graph: %.3f ms/rollout (fused speedup %.2fx)" % (pms, pms / fused_ms))
+    del g
+
+    # fused rollout captured as a graph as well (whole rollout = 1 replay)
+    traj2 = wm.State.empty((T, n), dev)
+    met2 = wm.Metrics.empty((T, n), dev)
+    ws1 = ds.batch.workspace(T, 10)
+
+    def fused():
+        wm.inverse_action(inv_batch, cur, nxt, scene.dt, ea, ek)
+        wm.rollout(ds.batch, ds.init, expert, ds.log_seq, ds.rg, T, scene.dt, ws1, traj=traj2, metrics=met2,
+                   tune=tune)
+
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fused()
+    torch.cuda.current_stream().wait_stream(side)
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        fused()
+    g2.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g2.replay()
+    torch.cuda.synchronize()
+    gms = 1e3 * (time.perf_counter() - t0) / reps
+    out["fused_graph"] = {"ms_per_rollout": gms, "value": n * T / (gms * 1e-3), "unit": "agent-steps/s"}
+    ok = all(torch.equal(getattr(met2, f), getattr(met, f)) for f in fields)
+    out["fused_graph"]["equals_plain"] = bool(ok)
+    del g2
+
+    # differentiable rollout: forward (every metric + loss + checkpoints) + adjoint
+    a = ea.clone().requires_grad_(True)
+    k = ek.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        a.grad = None
+        k.grad = None
+        L = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, ds.rg, T, scene.dt, 10)
+        L.sum().backward()
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_BACKWARD)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    fbms = 1e3 * (time.perf_counter() - t0) / reps
+    bms, bl = wm.profile_collect(wm.PROF_BACKWARD)
+    wm.profile_enable(False)
+    out["fwd_bwd"] = {"value": S * T / (fbms * 1e-3), "unit": "rollout scenario-steps/s",
+                      "agent_steps_per_s": n * T / (fbms * 1e-3), "ms_per_rollout": fbms,
+                      "backward_kernel_ms": bms / max(bl, 1), "controlled": "all objects",
+                      "checkpoint_every": 10}
+    log("fwd+bwd: %.3f ms/rollout (adjoint kernel %.3f ms)" % (fbms, bms / max(bl, 1)))
+
+    # observation: 8 egos per scenario, k = 1000 nearest road points
+    E, K = 8, 1000
+    idx = torch.empty(S * E * K, dtype=torch.int32, device=dev)
+    rf = torch.empty(S * E * K * 4, device=dev)
+    of = torch.empty(S * E * ds.batch.max_objects * 8, device=dev)
+    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_OBSERVE)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    oms = 1e3 * (time.perf_counter() - t0) / reps
+    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
+    wm.profile_enable(False)
+    out_bytes = S * E * (K * 20 + ds.batch.max_objects * 32)
+    okm = kms / max(kl, 1)
+    out["observe"] = {"egos_per_s": S * E / (oms * 1e-3), "ms": oms, "kernel_ms": okm, "k": K, "egos": S * E,
+                      "output_GBps": out_bytes / (okm * 1e-3) / 1e9}
+    log("observe: %.3f ms for %d egos (kernel %.3f ms)" % (oms, S * E, okm))
+
+
+if __name__ == "__main__":
+    main()

@@ -230,6 +230,20 @@ int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *ac
                 const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, void *ws,
                 size_t ws_bytes, wm_tuning *best, void *stream);
 
+/* Kernel timing, a profiling aid (not part of the paper's method).  While
+ * enabled (process-wide), wm_rollout, wm_rollout_backward, wm_observe
+ * and wm_offroad bracket their main kernel with HIP events on the caller's
+ * stream.  wm_profile_collect waits for the recorded events of one entry
+ * point (WM_PROF_*), returns the summed kernel time [ms] and the number of
+ * launches, and forgets them.  Event pairs are kept for up to 4096 launches
+ * per entry point; later launches are not recorded. */
+#define WM_PROF_ROLLOUT 0
+#define WM_PROF_BACKWARD 1
+#define WM_PROF_OBSERVE 2
+#define WM_PROF_OFFROAD 3
+int wm_profile_enable(int on);
+int wm_profile_collect(int which, float *total_ms, int32_t *launches);
+
 /* Static description of a return code. */
 const char *wm_error_string(int code);
 

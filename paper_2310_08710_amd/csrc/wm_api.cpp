@@ -11,6 +11,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "../../include/wm.h"
 #include "wm_internal.h"
@@ -149,6 +150,55 @@ size_t workspace_bytes(const wm_batch *b, int T, int K)
     return wm::ws_layout(b->num_scenarios, b->total_objects, b->total_rg_points, T, K).total;
 }
 
+// ---- kernel timing (profiling aid) ----
+constexpr int kProfKinds = 4;
+constexpr size_t kProfMax = 4096;
+struct ProfState {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> used[kProfKinds];
+    std::vector<hipEvent_t> pool;   // reused; never destroyed (no HIP calls at thread or process exit)
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        return e;
+    }
+};
+// process-wide: autograd runs backward passes on its own threads
+ProfState g_prof;
+std::mutex g_prof_mu;
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int k, hipStream_t s) : kind(k), st(s)
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (g_prof.on && g_prof.used[kind].size() < kProfMax) {
+            a = g_prof.get();
+            b = g_prof.get();
+            if (a && b)
+                (void)hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, st);
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            g_prof.used[kind].emplace_back(a, b);
+        }
+    }
+};
+
 } // namespace
 
 extern "C" {
@@ -175,6 +225,43 @@ const char *wm_error_string(int code)
 }
 
 const char *wm_last_error_message(void) { return g_msg.c_str(); }
+
+int wm_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.on = on != 0;
+    return ok();
+}
+
+int wm_profile_collect(int which, float *total_ms, int32_t *launches)
+{
+    if (which < 0 || which >= kProfKinds)
+        return fail(WM_ERR_RANGE, "profile kind %d out of range", which);
+    if (!total_ms || !launches)
+        return fail(WM_ERR_NULL, "total_ms or launches is NULL");
+    float tot = 0.f;
+    int cnt = 0;
+    int rc = WM_OK;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &p : g_prof.used[which]) {
+        float ms = 0.f;
+        if (rc == WM_OK) {
+            hipError_t e = hipEventSynchronize(p.second);
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, p.first, p.second);
+            if (e != hipSuccess)
+                rc = fail(WM_ERR_DEVICE, "wm_profile_collect: %s", hipGetErrorString(e));
+            tot += ms;
+            ++cnt;
+        }
+        g_prof.pool.push_back(p.first);
+        g_prof.pool.push_back(p.second);
+    }
+    g_prof.used[which].clear();
+    *total_ms = tot;
+    *launches = cnt;
+    return rc == WM_OK ? ok() : rc;
+}
 
 int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
             const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
@@ -267,7 +354,10 @@ int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
     wm::OffroadArgs o{batch->obj_off, batch->rg_off, *st, (const float2 *)(w + L.exy), (const float2 *)(w + L.edir),
                       (const int32_t *)(w + L.eidx), (const int32_t *)(w + L.ecount), offroad, margin, nearest_idx,
                       tn.G, tn.CW};
-    wm::launch_offroad(*batch, o, s);
+    {
+        ProfScope ps(WM_PROF_OFFROAD, s);
+        wm::launch_offroad(*batch, o, s);
+    }
     return device_status("wm_offroad");
 }
 
@@ -291,7 +381,10 @@ int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
         return fail(WM_ERR_UNSUPPORTED, "S * E * k too large");
     wm::ObserveArgs a{batch->obj_off, batch->rg_off, *st, *rg, ego, E, k, batch->max_objects, rg_idx, rg_feat,
                       obj_feat};
-    wm::launch_observe(*batch, a, (hipStream_t)stream);
+    {
+        ProfScope ps(WM_PROF_OBSERVE, (hipStream_t)stream);
+        wm::launch_observe(*batch, a, (hipStream_t)stream);
+    }
     return device_status("wm_observe");
 }
 
@@ -374,7 +467,10 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
     const int U = 64 * tn.CW;
     const int bound = batch->total_objects / U + batch->num_scenarios;
     const int grid = wm::rollout_grid(tn.G, tn.CW, batch->max_objects, bound);
-    wm::launch_rollout(a, grid, s);
+    {
+        ProfScope ps(WM_PROF_ROLLOUT, s);
+        wm::launch_rollout(a, grid, s);
+    }
     if (loss)
         wm::launch_loss_reduce(batch->num_scenarios, a.uoff, a.lossp, loss, s);
     return device_status("wm_rollout");
@@ -410,7 +506,10 @@ int wm_rollout_backward(const wm_batch *batch, const wm_state *init, const wm_ac
     a.grad_a = grad_accel;
     a.grad_k = grad_curvature;
     a.seg = (float *)((unsigned char *)ws + L.seg);
-    wm::launch_backward(a, (hipStream_t)stream);
+    {
+        ProfScope ps(WM_PROF_BACKWARD, (hipStream_t)stream);
+        wm::launch_backward(a, (hipStream_t)stream);
+    }
     return device_status("wm_rollout_backward");
 }
 

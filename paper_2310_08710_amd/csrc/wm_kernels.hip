@@ -13,6 +13,10 @@
 //                    + training loss + checkpoints per work unit
 //   k_loss_reduce    deterministic per-scenario sum of the loss partials
 //   k_observe, k_rollout_backward live in their own sections below.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "wm_device.h"
 #include "wm_internal.h"
 
@@ -697,19 +701,37 @@ size_t rollout_lds_bytes(int maxN, int G, int CW)
 
 int rollout_grid(int G, int CW, int maxN, int n_units_bound)
 {
-    const int nthr = 64 * CW * G;
-    const size_t lds = rollout_lds_bytes(maxN, G, CW);
-    if (lds > 65536)
-        hipFuncSetAttribute((const void *)k_rollout, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rollout, nthr, lds) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (cus < 1)
-        cus = 1;
-    const long grid = (long)per_cu * cus;
+    // resident work-groups per device for this launch shape; queried once per
+    // (device, shape) so that later calls (e.g. under graph capture) make no
+    // runtime queries
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, long> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, G, CW, maxN);
+    long grid = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end())
+            grid = it->second;
+    }
+    if (grid == 0) {
+        const int nthr = 64 * CW * G;
+        const size_t lds = rollout_lds_bytes(maxN, G, CW);
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_rollout, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rollout, nthr, lds) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        int cus = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus < 1)
+            cus = 1;
+        grid = (long)per_cu * cus;
+        std::lock_guard<std::mutex> lk(mu);
+        cache[key] = grid;
+    }
     return (int)(grid < n_units_bound ? grid : (n_units_bound < 1 ? 1 : n_units_bound));
 }
 

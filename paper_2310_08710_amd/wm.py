@@ -91,6 +91,8 @@ def lib() -> C.CDLL:
         L.wm_rollout_backward.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction),
                                           C.POINTER(CState), C.c_int32, C.c_float, C.c_int32, C.POINTER(CState),
                                           _P, _P, _P, _P, C.c_size_t, _P]
+        L.wm_profile_enable.argtypes = [C.c_int]
+        L.wm_profile_collect.argtypes = [C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
         L.wm_autotune.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
                                   C.POINTER(CRoadgraph), C.c_int32, C.c_float, _P, C.c_size_t, C.POINTER(CTuning),
                                   _P]
@@ -316,6 +318,22 @@ def autotune(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: Opt
     _check(lib().wm_autotune(C.byref(b), C.byref(i), C.byref(a), C.byref(l), C.byref(r) if r is not None else None,
                              T, dt, ws.data_ptr(), ws.numel(), C.byref(best), _stream(stream)))
     return best.unit_objects, best.edge_splits
+
+
+PROF_ROLLOUT, PROF_BACKWARD, PROF_OBSERVE, PROF_OFFROAD = range(4)
+
+
+def profile_enable(on: bool = True):
+    _check(lib().wm_profile_enable(1 if on else 0))
+
+
+def profile_collect(which: int):
+    """(total kernel ms, launches) of one entry point's main kernel since the
+    last collect (waits for the recorded events)."""
+    ms = C.c_float(0.0)
+    cnt = C.c_int32(0)
+    _check(lib().wm_profile_collect(which, C.byref(ms), C.byref(cnt)))
+    return float(ms.value), int(cnt.value)
 
 
 class RolloutLoss(torch.autograd.Function):
