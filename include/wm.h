@@ -112,10 +112,18 @@ typedef struct wm_action {
  *   overlap_margin  max over partners of the separating-axis margin
  *   offroad         1 iff some box corner lies right of its nearest road edge
  *   offroad_margin  max over the 4 corners of the signed side distance
- *   log_div         |xy - xy_log| when both are valid, else 0 */
+ *   log_div         |xy - xy_log| when both are valid, else 0
+ *   infeasible      kinematic infeasibility of the transition into this state
+ *                   (Sec. 3.4): the bicycle inverse of (previous, successor)
+ *                   has |a| > 6 m/s^2 or |kappa| > 0.3 1/m; 0 unless both
+ *                   states are valid
+ *   reward          -1[collision] - 1[off-road] (the sparse reward of Sec. 5.2);
+ *                   requires collision and, with a road graph, offroad */
 typedef struct wm_metrics {
     uint8_t *collision, *offroad;
     float *overlap_margin, *offroad_margin, *log_div;
+    uint8_t *infeasible;
+    float *reward;
 } wm_metrics;
 
 /* Optional launch tuning of the off-road / rollout kernels; NULL selects the
@@ -153,6 +161,35 @@ int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act,
  * otherwise).  Outputs hold total_objects entries; valid_out may be NULL. */
 int wm_inverse_action(const wm_batch *batch, const wm_state *cur, const wm_state *next, float dt,
                       float *accel, float *curvature, uint8_t *valid_out, void *stream);
+
+/* Delta actions (App. A.1, delta action space): increments of x, y and yaw
+ * per step ([total_objects] each) plus the control mask, as for wm_action. */
+typedef struct wm_delta_action {
+    const float *dx, *dy, *dyaw;
+    const uint8_t *controlled;
+} wm_delta_action;
+
+/* One step in the delta action space (App. A.1, delta equations):
+ * x' = x + dx, y' = y + dy, yaw' = yaw + dyaw, (vx', vy') = ((x' - x), (y' - y)) / dt,
+ * with the control semantics of wm_step (playback / frozen).  Dynamics only:
+ * metrics of `next` come from wm_overlap / wm_offroad. */
+int wm_step_delta(const wm_batch *batch, const wm_state *cur, const wm_delta_action *act,
+                  const wm_state *log_next, float dt, wm_state *next, void *stream);
+
+/* Inverse of the delta step (App. A.1): (dx, dy, dyaw) = s' - s; zero and
+ * valid_out = 0 unless both states are valid.  valid_out may be NULL. */
+int wm_inverse_delta(const wm_batch *batch, const wm_state *cur, const wm_state *next, float *dx, float *dy,
+                     float *dyaw, uint8_t *valid_out, void *stream);
+
+/* Discretized actions (Sec. 5.2, Expert: the discrete inverse is the
+ * continuous inverse discretized): each of the n values maps to the nearest
+ * of `bins` (>= 2) evenly spaced values over [lo, hi] (lo < hi, finite);
+ * half-way values go to the upper one, values outside the range to the end
+ * bins.  Decided in binary32 as index = floor((v - lo) * s + 0.5) with
+ * s = fl((bins - 1) / (hi - lo)); snapped = lo + index * fl((hi - lo) / (bins - 1)).
+ * values/index/snapped are device arrays of n entries; snapped may be NULL. */
+int wm_discretize(const float *values, int32_t n, float lo, float hi, int32_t bins, int32_t *index,
+                  float *snapped, void *stream);
 
 /* Collision metric (Sec. 3.4, Collision: 2D top-down box overlap) by the
  * separating-axis test.  For every object: collision (u8) and max_margin

@@ -124,6 +124,32 @@ def bicycle_inverse(cur, nxt, dt):
     return a, k, v
 
 
+def infeasibility(cur, nxt, dt):
+    """Kinematic infeasibility of each transition, Sec. 3.4: inverse
+    kinematics gives |a| > 6 m/s^2 or |kappa| > 0.3 1/m.  uint8 [n]."""
+    cs, ns = OState(cur), OState(nxt)
+    n = cs.a["x"].shape[0]
+    out = np.zeros(n, np.uint8)
+    lib().or_infeasibility(C.c_int(n), C.byref(cs.c), C.byref(ns.c), C.c_double(dt), _p(out, C.c_uint8))
+    return out
+
+
+def reward(collision, offroad):
+    """Sparse per-object reward of Sec. 5.2: -1[collision] - 1[off-road]."""
+    return -(np.asarray(collision, np.float64) + np.asarray(offroad, np.float64))
+
+
+def discretize(values, lo: float, hi: float, bins: int):
+    """Discretized actions (Sec. 5.2): nearest of `bins` evenly spaced values
+    over [lo, hi], decided in binary32.  Returns (index int32, snapped float32)."""
+    v = np.ascontiguousarray(values, dtype=np.float32).reshape(-1)
+    idx = np.zeros(v.shape[0], np.int32)
+    snp = np.zeros(v.shape[0], np.float32)
+    lib().or_discretize(C.c_int(v.shape[0]), _p(v, C.c_float), C.c_float(lo), C.c_float(hi), C.c_int(bins),
+                        _p(idx, C.c_int32), _p(snp, C.c_float))
+    return idx, snp
+
+
 def delta_forward(cur, dx, dy, dyaw, controlled, log_next, dt):
     """Delta action space forward step, App. A.1 (delta equations)."""
     cs, ls = OState(cur), OState(log_next)

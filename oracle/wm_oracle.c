@@ -155,6 +155,24 @@ void or_bicycle_inverse(int n, const or_state *cur, const or_state *nxt, double 
 }
 
 /* ------------------------------------------------------------------------
+ * Kinematic infeasibility (Sec. 3.4): the bicycle inverse kinematics of a
+ * transition (cur -> nxt) gives (a, kappa); the transition is infeasible when
+ * |a| > 6 m/s^2 or |kappa| > 0.3 1/m (strict).  0 unless both states are valid.
+ * ---------------------------------------------------------------------- */
+void or_infeasibility(int n, const or_state *cur, const or_state *nxt, double dt, uint8_t *out)
+{
+    double *a = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *k = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    uint8_t *v = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    or_bicycle_inverse(n, cur, nxt, dt, a, k, v);
+    for (int i = 0; i < n; ++i)
+        out[i] = (uint8_t)(v[i] && (fabs(a[i]) > 6.0 || fabs(k[i]) > 0.3));
+    free(a);
+    free(k);
+    free(v);
+}
+
+/* ------------------------------------------------------------------------
  * Delta action space, App. A.1 (delta forward and inverse equations):
  *   x' = x + dx, y' = y + dy, yaw' = yaw + dyaw,
  *   vx' = (x' - x)/dt, vy' = (y' - y)/dt;   inverse: d = s' - s.
@@ -195,6 +213,42 @@ void or_delta_inverse(int n, const or_state *cur, const or_state *nxt,
         dy[i] = ok ? nxt->y[i] - cur->y[i] : 0.0;
         dyaw[i] = ok ? nxt->yaw[i] - cur->yaw[i] : 0.0;
         valid[i] = (uint8_t)ok;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Discretized actions (Sec. 5.2, Expert: "the inverse is computed by
+ * discretizing the continuous inverse").  Reading: `bins` values evenly
+ * spaced over [lo, hi] (bins >= 2); each value maps to the nearest one, a
+ * value half-way between two goes to the upper one, values outside the range
+ * to the end bins.  The index is an integer decided by floating point, so it
+ * is computed in the kernel's precision (binary32) with a fixed operation
+ * order: u = (v - lo) * ((bins - 1) / (hi - lo)), index = floor(u + 0.5).
+ * ---------------------------------------------------------------------- */
+void or_discretize(int n, const float *values, float lo, float hi, int bins, int32_t *index, float *snapped)
+{
+    volatile float scale = (float)(bins - 1) / (hi - lo);
+    volatile float step = (hi - lo) / (float)(bins - 1);
+    for (int i = 0; i < n; ++i) {
+        volatile float d = values[i] - lo;
+        volatile float u = d * scale;
+        volatile float w = u + 0.5f;
+        int k;
+        if (!(w >= 0.0f))
+            k = 0;
+        else if (w >= (float)bins)
+            k = bins - 1;
+        else
+            k = (int)floorf(w);
+        if (k > bins - 1)
+            k = bins - 1;
+        if (k < 0)
+            k = 0;
+        index[i] = k;
+        if (snapped) {
+            volatile float kv = (float)k * step;
+            snapped[i] = lo + kv;
+        }
     }
 }
 

@@ -279,11 +279,14 @@ int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, co
     const bool want_off = m && rg && (m->offroad || m->offroad_margin);
     if (want_off)
         CHECK(check_rg(rg));
+    if (m && m->reward && (!m->collision || (rg && !m->offroad)))
+        return fail(WM_ERR_NULL, "reward needs the collision (and, with a road graph, offroad) outputs");
     const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
     if (want_off)
         CHECK(check_ws(ws, ws_bytes, L.total));
     hipStream_t st = (hipStream_t)stream;
-    wm::StepArgs a{batch->obj_off, *cur, *act, *log_next, *next, dt, m ? m->log_div : nullptr};
+    wm::StepArgs a{batch->obj_off, *cur, *act, *log_next, *next, dt, m ? m->log_div : nullptr,
+                   m ? m->infeasible : nullptr};
     wm::launch_dynamics(*batch, a, st);
     if (m && (m->collision || m->overlap_margin)) {
         wm::OverlapArgs o{batch->obj_off, *next, nullptr, nullptr, nullptr, m->collision, m->overlap_margin,
@@ -298,11 +301,12 @@ int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, co
         if (tn.G > 16)
             tn.G = 16;
         wm::launch_compact_edges(*batch, *rg, w, L, st);
-        wm::OffroadArgs o{batch->obj_off, batch->rg_off, *next, (const float2 *)(w + L.exy),
-                          (const float2 *)(w + L.edir), (const int32_t *)(w + L.eidx),
-                          (const int32_t *)(w + L.ecount), m->offroad, m->offroad_margin, nullptr, tn.G, tn.CW};
+        wm::OffroadArgs o{batch->obj_off, batch->rg_off, *next, wm::ws_edges(w, L), m->offroad, m->offroad_margin,
+                          nullptr, tn.G, tn.CW};
         wm::launch_offroad(*batch, o, st);
     }
+    if (m && m->reward)
+        wm::launch_reward(*batch, m->collision, rg ? m->offroad : nullptr, m->reward, st);
     return device_status("wm_step");
 }
 
@@ -318,6 +322,54 @@ int wm_inverse_action(const wm_batch *batch, const wm_state *cur, const wm_state
     if (batch->total_objects > 0)
         wm::launch_inverse(batch->total_objects, *cur, *next, dt, accel, curvature, valid_out, (hipStream_t)stream);
     return device_status("wm_inverse_action");
+}
+
+int wm_step_delta(const wm_batch *batch, const wm_state *cur, const wm_delta_action *act, const wm_state *log_next,
+                  float dt, wm_state *next, void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(cur, "cur"));
+    CHECK(check_state(log_next, "log_next"));
+    CHECK(check_state(next, "next"));
+    if (!act || !act->dx || !act->dy || !act->dyaw || !act->controlled)
+        return fail(WM_ERR_NULL, "delta action is NULL or has a NULL member");
+    CHECK(check_dt(dt));
+    if (next->x == cur->x)
+        return fail(WM_ERR_RANGE, "next must not alias cur");
+    wm::launch_delta_step(*batch, *cur, *act, *log_next, *next, dt, (hipStream_t)stream);
+    return device_status("wm_step_delta");
+}
+
+int wm_inverse_delta(const wm_batch *batch, const wm_state *cur, const wm_state *next, float *dx, float *dy,
+                     float *dyaw, uint8_t *valid_out, void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(cur, "cur"));
+    CHECK(check_state(next, "next"));
+    if (!dx || !dy || !dyaw)
+        return fail(WM_ERR_NULL, "dx/dy/dyaw output is NULL");
+    if (batch->total_objects > 0)
+        wm::launch_delta_inverse(batch->total_objects, *cur, *next, dx, dy, dyaw, valid_out, (hipStream_t)stream);
+    return device_status("wm_inverse_delta");
+}
+
+int wm_discretize(const float *values, int32_t n, float lo, float hi, int32_t bins, int32_t *index, float *snapped,
+                  void *stream)
+{
+    if (n < 0)
+        return fail(WM_ERR_RANGE, "n = %d < 0", n);
+    if (n > 0 && (!values || !index))
+        return fail(WM_ERR_NULL, "values or index is NULL");
+    if (bins < 2)
+        return fail(WM_ERR_RANGE, "bins = %d < 2", bins);
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi))
+        return fail(WM_ERR_RANGE, "need finite lo < hi (lo = %g, hi = %g)", (double)lo, (double)hi);
+    volatile float span = hi - lo;
+    volatile float scale = (float)(bins - 1) / span;
+    volatile float step = span / (float)(bins - 1);
+    if (n > 0)
+        wm::launch_discretize(n, values, lo, scale, step, bins, index, snapped, (hipStream_t)stream);
+    return device_status("wm_discretize");
 }
 
 int wm_overlap(const wm_batch *batch, const wm_state *st, const int64_t *pair_off, float *margin, uint8_t *mask,
@@ -351,9 +403,8 @@ int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
     hipStream_t s = (hipStream_t)stream;
     unsigned char *w = (unsigned char *)ws;
     wm::launch_compact_edges(*batch, *rg, w, L, s);
-    wm::OffroadArgs o{batch->obj_off, batch->rg_off, *st, (const float2 *)(w + L.exy), (const float2 *)(w + L.edir),
-                      (const int32_t *)(w + L.eidx), (const int32_t *)(w + L.ecount), offroad, margin, nearest_idx,
-                      tn.G, tn.CW};
+    wm::OffroadArgs o{batch->obj_off, batch->rg_off, *st, wm::ws_edges(w, L), offroad, margin, nearest_idx, tn.G,
+                      tn.CW};
     {
         ProfScope ps(WM_PROF_OFFROAD, s);
         wm::launch_offroad(*batch, o, s);
@@ -450,10 +501,7 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
     a.has_ckpt = ckpt != nullptr;
     a.has_traj = traj != nullptr;
     a.want_loss = loss != nullptr;
-    a.exy = (const float2 *)(w + L.exy);
-    a.edir = (const float2 *)(w + L.edir);
-    a.eidx = (const int32_t *)(w + L.eidx);
-    a.ecount = (const int32_t *)(w + L.ecount);
+    a.E = wm::ws_edges(w, L);
     if (ckpt)
         a.ckpt = *ckpt;
     if (traj)

@@ -12,10 +12,11 @@
 #include <stdint.h>
 
 #include "../../include/wm.h"
+#include "wm_internal.h"
 
 namespace wm {
 
-constexpr int kChunk = 32;            // road-edge points per chunk of the off-road scan
+constexpr int kChunk = kEdgeChunk;    // road-edge points per chunk of the off-road scan
 constexpr float kNoValue = -FLT_MAX;  // margin with no defined value
 constexpr float kSoftScale = 0.1f;    // soft-overlap scale of the training loss [m]
 
@@ -26,7 +27,7 @@ typedef const float __attribute__((address_space(4))) *uniform_fptr;
 // Scenario-major packed state kept in LDS by the fused kernels.
 struct ObjLds {
     float *x, *y, *yaw, *vx, *vy, *len, *wid, *c, *s;
-    uint8_t *valid, *ctrl;
+    uint8_t *valid, *ctrl, *infeas;
 };
 
 // ---------------------------------------------------------------------------
@@ -66,6 +67,28 @@ __device__ __forceinline__ float wrap_angle(float a)
     if (r < -3.14159265358979323846f)
         r += two_pi;
     return r;
+}
+
+// Bicycle inverse kinematics (App. A.1, inverse kinematics equation) of one
+// transition: a = (|v'| - |v|) / dt, kappa = wrap(atan2(vy', vx') - yaw) / D with
+// D = |v| dt + a dt^2 / 2 (kappa = 0 when |D| < 1e-6 m).
+__device__ __forceinline__ void inverse_kinematics(float vx, float vy, float yaw, float nvx, float nvy, float dt,
+                                                   float &a, float &k)
+{
+    const float v = sqrtf(__builtin_fmaf(vy, vy, vx * vx));
+    const float nv = sqrtf(__builtin_fmaf(nvy, nvy, nvx * nvx));
+    a = (nv - v) / dt;
+    const float dist = __builtin_fmaf(v, dt, 0.5f * a * dt * dt);
+    k = fabsf(dist) < 1e-6f ? 0.f : wrap_angle(atan2f(nvy, nvx) - yaw) / dist;
+}
+
+// Kinematic infeasibility of a transition (Sec. 3.4): |a| > 6 or |kappa| > 0.3.
+__device__ __forceinline__ uint8_t infeasible_transition(float vx, float vy, float yaw, float nvx, float nvy,
+                                                         float dt)
+{
+    float a, k;
+    inverse_kinematics(vx, vy, yaw, nvx, nvy, dt, a, k);
+    return (uint8_t)(fabsf(a) > 6.f || fabsf(k) > 0.3f);
 }
 
 // ---------------------------------------------------------------------------
@@ -151,53 +174,127 @@ __device__ __forceinline__ float edge_d2(float qx, float qy, float cx, float cy)
 
 // ---------------------------------------------------------------------------
 // Off-road scan (the hot loop).  A wave scans chunks [c0, c1) of one
-// scenario's compacted road-edge list (x, y interleaved; padded with +inf
-// points to whole chunks) against R corners held per lane.  The edge address
-// is wave-uniform, so every point arrives once per wave through SMEM and is
-// used as an SGPR operand by all 64 lanes.  Only the minimum is tracked in the
-// inner loop; the first chunk that reaches the final minimum is remembered
-// (strict <), and the exact lowest index is recovered later by rescanning that
-// one chunk.
+// scenario's compacted road-edge stream (Edges) against R corners held per
+// lane.  The edge address is wave-uniform, so every point arrives once per
+// wave by a scalar load and is an SGPR operand for all 64 lanes.
+//
+// The inner loop evaluates the expanded form
+//     T(q) = |q|^2 - 2 c.q  ( = |q - c|^2 - |c|^2 )
+// as fma(-2cy, qy, fma(-2cx, qx, qq)): two FMAs and half a v_min3 per
+// (corner, point).  T is only used to select candidate chunks: per corner the
+// three smallest chunk minima are kept (values b1 <= b2 <= b3, chunk indices
+// of the first two).  Rounding of T and of the direct distance
+// D = fl(fl(dx^2) + dy^2) are both below 4u (|q| + |c|)^2 (u = 2^-24), so any
+// chunk whose T-minimum exceeds the best one by more than
+//     delta = 2^-19 (Rq + |c|)^2      (Rq = max |q| of the scenario)
+// cannot hold a point whose D is the minimum.  The candidate chunks (one or
+// two; otherwise the whole list) are then rescanned with D, and the lowest
+// index of the minimum of D is the nearest point -- the same result as an
+// exact scan of D over all points.
 // ---------------------------------------------------------------------------
-template <int R>
-__device__ __forceinline__ void scan_edges(const float *__restrict__ exy, int c0, int c1, const float (&cx)[R],
-                                           const float (&cy)[R], float (&best)[R], int (&bchunk)[R])
+constexpr int kChunkFloats = 3 * kChunk;
+
+__device__ __forceinline__ float candidate_band(float qqmax, float cx, float cy)
 {
-    uniform_fptr e = (uniform_fptr)exy;
+    const float r = sqrtf(qqmax) + sqrtf(__builtin_fmaf(cy, cy, cx * cx));
+    return 0x1p-19f * r * r;
+}
+
+template <int R>
+__device__ __forceinline__ void scan_edges(const float *__restrict__ stream, int c0, int c1, const float (&cx)[R],
+                                           const float (&cy)[R], float (&b1)[R], float (&b2)[R], float (&b3)[R],
+                                           int (&i1)[R], int (&i2)[R])
+{
+    c0 = __builtin_amdgcn_readfirstlane(c0);
+    c1 = __builtin_amdgcn_readfirstlane(c1);
+    if (c0 >= c1)
+        return;
+    uniform_fptr e = (uniform_fptr)stream;
+    float m2x[R], m2y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        m2x[r] = -2.0f * cx[r];
+        m2y[r] = -2.0f * cy[r];
+    }
     for (int c = c0; c < c1; ++c) {
         float m[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
             m[r] = __builtin_inff();
-        uniform_fptr p = e + 2 * kChunk * c;
-#pragma unroll
+        uniform_fptr p = e + kChunkFloats * c;
+#pragma unroll 16
         for (int j = 0; j < kChunk; ++j) {
-            const float qx = p[2 * j], qy = p[2 * j + 1];
+            const float qx = p[j], qy = p[kChunk + j], qq = p[2 * kChunk + j];
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                m[r] = fminf(m[r], edge_d2(qx, qy, cx[r], cy[r]));
+                m[r] = fminf(m[r], __builtin_fmaf(m2y[r], qy, __builtin_fmaf(m2x[r], qx, qq)));
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (m[r] < best[r]) {
-                best[r] = m[r];
-                bchunk[r] = c;
+            const bool lt1 = m[r] < b1[r], lt2 = m[r] < b2[r];
+            b3[r] = __builtin_amdgcn_fmed3f(b2[r], b3[r], m[r]);
+            b2[r] = __builtin_amdgcn_fmed3f(b1[r], b2[r], m[r]);
+            b1[r] = fminf(b1[r], m[r]);
+            i2[r] = lt1 ? i1[r] : (lt2 ? c : i2[r]);
+            i1[r] = lt1 ? c : i1[r];
+        }
+    }
+}
+
+// Exact rescan of chunk `c` for one corner (per lane): lowest index of the
+// minimum of D over the chunk's real points (index < E), folded into
+// (best, bidx) with strict <, so chunks rescanned in ascending order keep the
+// lowest index.  The chunk's x and y columns arrive as 16-byte vector loads
+// issued together (chunks are 16-byte aligned in the workspace).
+__device__ __forceinline__ void rescan_chunk(const float *__restrict__ stream, int c, int E, float cx, float cy,
+                                             float &best, int &bidx)
+{
+    const float4 *px = (const float4 *)(stream + kChunkFloats * c);
+    const float4 *py = (const float4 *)(stream + kChunkFloats * c + kChunk);
+    const int n = E - kChunk * c;
+#pragma unroll
+    for (int b = 0; b < kChunk / 4; ++b) {
+        const float4 X = px[b], Y = py[b];
+        const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = 4 * b + k;
+            const float d = edge_d2(xs[k], ys[k], cx, cy);
+            if (j < n && d < best) {
+                best = d;
+                bidx = kChunk * c + j;
             }
         }
     }
 }
 
-// Lowest index j in chunk `c` whose distance equals `best` (vector loads).
-__device__ __forceinline__ int rescan_chunk(const float2 *__restrict__ exy, int c, float cx, float cy, float best)
+// Exact scan of every chunk for one corner by a whole wave (the corner is
+// wave-uniform): lane l takes point l of each chunk, then a wave reduction on
+// (D, index) keeps the lowest index of the minimum.  Returns the point index
+// (or -1) in every lane.
+__device__ __forceinline__ int wave_full_scan(const float *__restrict__ stream, int nch, int E, float cx, float cy)
 {
-    const float2 *p = exy + kChunk * c;
-    int found = kChunk - 1;   // always inside the chunk, even if no bit-equal match existed
-    for (int j = kChunk - 1; j >= 0; --j) {
-        const float2 q = p[j];
-        if (edge_d2(q.x, q.y, cx, cy) == best)
-            found = j;
+    const int lane = threadIdx.x & 63;
+    float best = __builtin_inff();
+    int bj = 0x7fffffff;
+    for (int c = 0; c < nch; ++c) {
+        const int j = kChunk * c + lane;
+        const float *p = stream + kChunkFloats * c;
+        const float d = edge_d2(p[lane], p[kChunk + lane], cx, cy);
+        if (j < E && d < best) {
+            best = d;
+            bj = j;
+        }
     }
-    return kChunk * c + found;
+    for (int o = 32; o > 0; o >>= 1) {
+        const float ob = __shfl_xor(best, o);
+        const int oj = __shfl_xor(bj, o);
+        if (ob < best || (ob == best && oj < bj)) {
+            best = ob;
+            bj = oj;
+        }
+    }
+    return bj == 0x7fffffff ? -1 : bj;
 }
 
 } // namespace wm

@@ -12,6 +12,31 @@ namespace wm {
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Road-edge points per chunk of the off-road scan.
+constexpr int kEdgeChunk = 64;
+
+// First point slot of scenario s in the compacted road-edge arrays: a whole
+// number of chunks, at least P_s + 64 slots before the next scenario's.
+__host__ __device__ inline long edge_base(int rg_off_s, int s)
+{
+    return (long)kEdgeChunk * ((long)rg_off_s / kEdgeChunk + 2L * s);
+}
+
+// Compacted road edges in the workspace.  Scenario s owns the point slots
+// from edge_base(rg_off[s], s): its valid road edges in index order, padded
+// to whole chunks (two spare chunks at the end of the arrays let the scan
+// prefetch past the last chunk).  `stream` holds chunk c
+// of that range as x[64], y[64], qq[64] (qq = x^2 + y^2; padding points have
+// x = y = 0 and qq = +inf); `dir` and `idx` (scenario-local original index)
+// are indexed by point.  `count` = edges per scenario, `qqmax` = their max qq.
+struct Edges {
+    float *stream;
+    float2 *dir;
+    int32_t *idx;
+    int32_t *count;
+    float *qqmax;
+};
+
 struct StepArgs {
     const int32_t *obj_off;
     wm_state cur;
@@ -20,6 +45,7 @@ struct StepArgs {
     wm_state next;
     float dt;
     float *log_div;
+    uint8_t *infeasible;
 };
 
 struct OverlapArgs {
@@ -37,8 +63,7 @@ struct OverlapArgs {
 struct OffroadArgs {
     const int32_t *obj_off, *rg_off;
     wm_state st;
-    const float2 *exy, *edir;
-    const int32_t *eidx, *ecount;
+    Edges E;
     uint8_t *offroad;
     float *margin;
     int32_t *nearest;
@@ -53,8 +78,7 @@ struct RollArgs {
     wm_action act;
     wm_state log;
     int has_rg, has_ckpt, has_traj, want_loss;
-    const float2 *exy, *edir;
-    const int32_t *eidx, *ecount;
+    Edges E;
     wm_state ckpt, traj;
     wm_metrics met;
     float *lossp;
@@ -88,19 +112,20 @@ struct BackwardArgs {
 
 // Workspace sections (byte offsets, each 256-aligned).
 struct WsLayout {
-    size_t ecount, exy, edir, eidx, uoff, units, lossp, counter, seg, total;
+    size_t ecount, stream, edir, eidx, qqmax, uoff, units, lossp, counter, seg, total;
 };
 
 inline WsLayout ws_layout(int S, int n, int P, int T, int K)
 {
-    const size_t cap = (size_t)P + (size_t)S * 32 + 32;
+    const size_t cap = (size_t)P + 2 * (size_t)S * kEdgeChunk + 2 * kEdgeChunk;
     WsLayout L;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
     L.ecount = take(sizeof(int32_t) * (size_t)S);
-    L.exy = take(sizeof(float) * 2 * cap);
+    L.stream = take(sizeof(float) * 3 * cap);
     L.edir = take(sizeof(float) * 2 * cap);
     L.eidx = take(sizeof(int32_t) * cap);
+    L.qqmax = take(sizeof(float) * (size_t)S);
     L.uoff = take(sizeof(int32_t) * ((size_t)S + 1));
     L.units = take(sizeof(int32_t) * 2 * ((size_t)n + 1));
     L.lossp = take(sizeof(float) * ((size_t)n + 1));
@@ -110,6 +135,12 @@ inline WsLayout ws_layout(int S, int n, int P, int T, int K)
     return L;
 }
 
+inline Edges ws_edges(unsigned char *ws, const WsLayout &L)
+{
+    return Edges{(float *)(ws + L.stream), (float2 *)(ws + L.edir), (int32_t *)(ws + L.eidx),
+                 (int32_t *)(ws + L.ecount), (float *)(ws + L.qqmax)};
+}
+
 // Launchers (wm_kernels.hip).  They only enqueue; errors surface through
 // hipGetLastError in the caller.
 void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned char *ws, const WsLayout &L,
@@ -117,6 +148,13 @@ void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned ch
 void launch_build_units(const wm_batch &b, int U, const int32_t *ecount, unsigned char *ws, const WsLayout &L,
                         hipStream_t st);
 void launch_dynamics(const wm_batch &b, const StepArgs &a, hipStream_t st);
+void launch_reward(const wm_batch &b, const uint8_t *col, const uint8_t *off, float *reward, hipStream_t st);
+void launch_delta_step(const wm_batch &b, const wm_state &cur, const wm_delta_action &act, const wm_state &log_next,
+                       const wm_state &next, float dt, hipStream_t st);
+void launch_delta_inverse(int n, const wm_state &cur, const wm_state &nxt, float *dx, float *dy, float *dyaw,
+                          uint8_t *vout, hipStream_t st);
+void launch_discretize(int n, const float *v, float lo, float scale, float step, int bins, int32_t *index,
+                       float *snapped, hipStream_t st);
 void launch_inverse(int n, const wm_state &cur, const wm_state &nxt, float dt, float *accel, float *curv,
                     uint8_t *vout, hipStream_t st);
 void launch_overlap(const wm_batch &b, const OverlapArgs &a, hipStream_t st);

@@ -23,24 +23,28 @@
 namespace wm {
 
 // ---------------------------------------------------------------------------
-// Road-edge compaction.  Scenario s owns workspace slots
-// [rg_off[s] + s * kChunk, rg_off[s+1] + (s+1) * kChunk): its E_s valid road
-// edges in index order, then +inf points up to a whole number of chunks.
+// Road-edge compaction into the workspace stream (layout in wm_internal.h,
+// struct Edges): the valid road edges of scenario s in index order, chunked
+// as x[64] y[64] qq[64], plus their directions, original indices, count and
+// the largest qq (it bounds the rounding of the scan's expanded distance).
 // ---------------------------------------------------------------------------
 template <int BT>
-__global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict__ rg_off, wm_roadgraph rg,
-                                                     float2 *__restrict__ exy, float2 *__restrict__ edir,
-                                                     int32_t *__restrict__ eidx, int32_t *__restrict__ ecount)
+__global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict__ rg_off, wm_roadgraph rg, Edges E)
 {
     __shared__ int wave_tot[BT / 64];
     __shared__ int run;
+    __shared__ unsigned int qqmax_bits;
     const int s = blockIdx.x;
     const int p0 = rg_off[s], p1 = rg_off[s + 1];
-    const int base = p0 + s * kChunk;
+    const long base = edge_base(p0, s);                // first point slot of the scenario
+    float *stream = E.stream + 3 * base;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         run = 0;
+        qqmax_bits = 0u;
+    }
     __syncthreads();
+    float my_max = 0.f;
     for (int j0 = p0; j0 < p1; j0 += BT) {
         const int j = j0 + threadIdx.x;
         const bool f = j < p1 && rg.valid[j] && rg.type[j] == WM_TYPE_ROAD_EDGE;
@@ -55,25 +59,38 @@ __global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict_
             total += wave_tot[i];
         }
         if (f) {
-            const int o = base + off + pre;
-            exy[o] = make_float2(rg.x[j], rg.y[j]);
-            edir[o] = make_float2(rg.dir_x[j], rg.dir_y[j]);
-            eidx[o] = j - p0;
+            const int o = off + pre;
+            const float x = rg.x[j], y = rg.y[j];
+            const float qq = __builtin_fmaf(y, y, x * x);
+            float *ch = stream + kChunkFloats * (o / kChunk) + (o % kChunk);
+            ch[0] = x;
+            ch[kChunk] = y;
+            ch[2 * kChunk] = qq;
+            E.dir[base + o] = make_float2(rg.dir_x[j], rg.dir_y[j]);
+            E.idx[base + o] = j - p0;
+            my_max = fmaxf(my_max, qq);
         }
         __syncthreads();
         if (threadIdx.x == 0)
             run += total;
         __syncthreads();
     }
-    const int E = run;
-    const int padded = (E + kChunk - 1) / kChunk * kChunk;
-    for (int j = E + threadIdx.x; j < padded; j += BT) {
-        exy[base + j] = make_float2(__builtin_inff(), __builtin_inff());
-        edir[base + j] = make_float2(0.f, 0.f);
-        eidx[base + j] = -1;
+    atomicMax(&qqmax_bits, __float_as_uint(my_max));   // qq >= 0: bit order = value order
+    const int cnt = run;
+    const int padded = (cnt + kChunk - 1) / kChunk * kChunk;
+    for (int o = cnt + threadIdx.x; o < padded; o += BT) {
+        float *ch = stream + kChunkFloats * (o / kChunk) + (o % kChunk);
+        ch[0] = 0.f;
+        ch[kChunk] = 0.f;
+        ch[2 * kChunk] = __builtin_inff();
+        E.dir[base + o] = make_float2(0.f, 0.f);
+        E.idx[base + o] = -1;
     }
-    if (threadIdx.x == 0)
-        ecount[s] = E;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        E.count[s] = cnt;
+        E.qqmax[s] = __uint_as_float(qqmax_bits);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -234,15 +251,53 @@ __device__ __forceinline__ void overlap_partial(const ObjLds &L, int N, int i0, 
     red[part * U + il] = mmax;
 }
 
-// Off-road scan of the 4*Ns corners of slice objects i0.. against the
-// scenario's compacted edges, followed by the rescan that recovers the
-// lowest-index nearest point and the signed side of every corner.
-// Waves: w = tid / 64, corner wave cw = w % CW (256 corner slots each),
-// edge split g = w / CW.  Leaves sk[slot] and nidx[slot] (scenario-local
-// point index or -1) for slot < 4*Ns.  Contains two block barriers.
-__device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float2 *__restrict__ exy,
-                             const float2 *__restrict__ edir, const int32_t *__restrict__ eidx, int nch, int G,
-                             int CW, float *sbest, int *schunk, float *sk, int *nidx)
+// Per-split candidate lists of the off-road scan in LDS: for every split g
+// and corner slot, the three smallest chunk minima and the first two chunks.
+struct ScanLds {
+    float *b1, *b2, *b3;
+    int *i1, *i2;
+    int *full;      // corner slots that need the exact scan of every chunk
+    int *nfull;
+};
+
+__device__ __forceinline__ ScanLds carve_scan(void *p, int G, int SL)
+{
+    float *f = (float *)p;
+    const int m = G * SL;
+    int *fl = (int *)(f + 5 * m);
+    return ScanLds{f, f + m, f + 2 * m, (int *)(f + 3 * m), (int *)(f + 4 * m), fl, fl + SL};
+}
+
+constexpr size_t scan_lds_bytes(int G, int CW) { return (size_t)G * 256 * CW * 20 + (size_t)256 * CW * 4 + 16; }
+
+template <int R>
+__device__ __forceinline__ void scan_r(const float *stream, int c0, int c1, const float (&cx)[4], const float (&cy)[4],
+                                       float (&b1)[4], float (&b2)[4], float (&b3)[4], int (&i1)[4], int (&i2)[4])
+{
+    float x[R], y[R], v1[R], v2[R], v3[R];
+    int j1[R], j2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        x[r] = cx[r]; y[r] = cy[r]; v1[r] = b1[r]; v2[r] = b2[r]; v3[r] = b3[r]; j1[r] = i1[r]; j2[r] = i2[r];
+    }
+    scan_edges<R>(stream, c0, c1, x, y, v1, v2, v3, j1, j2);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        b1[r] = v1[r]; b2[r] = v2[r]; b3[r] = v3[r]; i1[r] = j1[r]; i2[r] = j2[r];
+    }
+}
+
+// Off-road scan of the 4*Ns corners of slice objects i0.. against one
+// scenario's compacted edges (stream/dir/idx already offset to the scenario,
+// E edges, qqmax), then the exact rescan of the candidate chunks that yields
+// the lowest-index nearest point and the signed side of every corner.
+// Waves: w = tid / 64, corner wave cw = w % CW (256 corner slots each), edge
+// split g = w / CW (contiguous chunk ranges in index order).  Leaves sk[slot]
+// and nidx[slot] (scenario-local point index or -1) for slot < 4*Ns.
+// Contains two block barriers.
+__device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
+                             const float2 *__restrict__ edir, const int32_t *__restrict__ eidx, int E, float qqmax,
+                             int G, int CW, ScanLds C, float *sk, int *nidx)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
@@ -252,56 +307,52 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float2 *__re
     const int base = cw * 256;
     const int avail = nslots - base;
     const int Reff = avail <= 0 ? 0 : min(4, (avail + 63) >> 6);
+    const int nch = (E + kChunk - 1) / kChunk;
     const int cps = (nch + G - 1) / G;
     const int c0 = min(nch, g * cps), c1 = min(nch, c0 + cps);
-    float cx[4], cy[4], best[4];
-    int bch[4];
+    float cx[4], cy[4], b1[4], b2[4], b3[4];
+    int i1[4], i2[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         int slot = base + lane + 64 * r;
         slot = min(slot, max(nslots - 1, 0));
         const int o = i0 + (slot >> 2);
         box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, cx[r], cy[r]);
-        best[r] = __builtin_inff();
-        bch[r] = -1;
+        b1[r] = b2[r] = b3[r] = __builtin_inff();
+        i1[r] = i2[r] = -1;
     }
-    const float *ep = (const float *)exy;
-    if (Reff == 4) {
-        scan_edges<4>(ep, c0, c1, cx, cy, best, bch);
-    } else if (Reff == 3) {
-        float x3[3] = {cx[0], cx[1], cx[2]}, y3[3] = {cy[0], cy[1], cy[2]}, b3[3] = {best[0], best[1], best[2]};
-        int h3[3] = {bch[0], bch[1], bch[2]};
-        scan_edges<3>(ep, c0, c1, x3, y3, b3, h3);
-        for (int r = 0; r < 3; ++r) { best[r] = b3[r]; bch[r] = h3[r]; }
-    } else if (Reff == 2) {
-        float x2[2] = {cx[0], cx[1]}, y2[2] = {cy[0], cy[1]}, b2[2] = {best[0], best[1]};
-        int h2[2] = {bch[0], bch[1]};
-        scan_edges<2>(ep, c0, c1, x2, y2, b2, h2);
-        for (int r = 0; r < 2; ++r) { best[r] = b2[r]; bch[r] = h2[r]; }
-    } else if (Reff == 1) {
-        float x1[1] = {cx[0]}, y1[1] = {cy[0]}, b1[1] = {best[0]};
-        int h1[1] = {bch[0]};
-        scan_edges<1>(ep, c0, c1, x1, y1, b1, h1);
-        best[0] = b1[0];
-        bch[0] = h1[0];
-    }
+    if (tid == 0)
+        *C.nfull = 0;
+    if (Reff == 4)
+        scan_r<4>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
+    else if (Reff == 3)
+        scan_r<3>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
+    else if (Reff == 2)
+        scan_r<2>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
+    else if (Reff == 1)
+        scan_r<1>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int slot = base + lane + 64 * r;
         if (r < Reff && slot < nslots) {
-            sbest[g * SL + slot] = best[r];
-            schunk[g * SL + slot] = bch[r];
+            const int at = g * SL + slot;
+            C.b1[at] = b1[r];
+            C.b2[at] = b2[r];
+            C.b3[at] = b3[r];
+            C.i1[at] = i1[r];
+            C.i2[at] = i2[r];
         }
     }
     __syncthreads();
     for (int slot = tid; slot < nslots; slot += blockDim.x) {
+        // best chunk over the splits (ascending splits hold ascending chunks)
         float b = __builtin_inff();
         int bc = -1;
         for (int h = 0; h < G; ++h) {
-            const float v = sbest[h * SL + slot];
+            const float v = C.b1[h * SL + slot];
             if (v < b) {
                 b = v;
-                bc = schunk[h * SL + slot];
+                bc = C.i1[h * SL + slot];
             }
         }
         const int o = i0 + (slot >> 2);
@@ -310,15 +361,66 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float2 *__re
         if (bc >= 0 && L.valid[o]) {
             float x, y;
             box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
-            const int j = rescan_chunk(exy, bc, x, y, b);
-            const float2 q = exy[j], d = edir[j];
-            s_val = -__builtin_fmaf(d.x, y - q.y, -(d.y * (x - q.x)));
-            near = eidx[j];
+            const float lim = b + candidate_band(qqmax, x, y);
+            int other = -1;        // a second candidate chunk
+            bool full = false;     // three or more candidates: exact scan of every chunk
+            for (int h = 0; h < G; ++h) {
+                const int at = h * SL + slot;
+                if (C.b3[at] <= lim)
+                    full = true;
+                const int cand[2] = {C.i1[at], C.i2[at]};
+                const float val[2] = {C.b1[at], C.b2[at]};
+                for (int q = 0; q < 2; ++q) {
+                    if (val[q] <= lim && cand[q] != bc && cand[q] != other) {
+                        if (other < 0)
+                            other = cand[q];
+                        else
+                            full = true;
+                    }
+                }
+            }
+            float best = __builtin_inff();
+            int bj = -1;
+            if (full) {
+                // rare: left to a whole wave after the next barrier
+                C.full[atomicAdd(C.nfull, 1)] = slot;
+            } else {
+                const int lo = other >= 0 ? min(bc, other) : bc;
+                rescan_chunk(stream, lo, E, x, y, best, bj);
+                if (other >= 0)
+                    rescan_chunk(stream, max(bc, other), E, x, y, best, bj);
+            }
+            if (bj >= 0) {
+                const float *ch = stream + kChunkFloats * (bj / kChunk) + (bj % kChunk);
+                const float qx = ch[0], qy = ch[kChunk];
+                const float2 d = edir[bj];
+                s_val = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
+                near = eidx[bj];
+            }
         }
         sk[slot] = s_val;
         nidx[slot] = near;
     }
     __syncthreads();
+    const int nf = *C.nfull;
+    if (nf > 0) {
+        const int nw = blockDim.x >> 6;
+        for (int f = w; f < nf; f += nw) {
+            const int slot = C.full[f];
+            const int o = i0 + (slot >> 2);
+            float x, y;
+            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+            const int bj = wave_full_scan(stream, nch, E, x, y);
+            if (lane == 0 && bj >= 0) {
+                const float *ch = stream + kChunkFloats * (bj / kChunk) + (bj % kChunk);
+                const float qx = ch[0], qy = ch[kChunk];
+                const float2 d = edir[bj];
+                sk[slot] = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
+                nidx[slot] = eidx[bj];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ void load_object(ObjLds &L, int i, const wm_state &st, long g)
@@ -366,7 +468,8 @@ __device__ __forceinline__ unsigned char *carve_objects(unsigned char *p, int ma
     uint8_t *b = (uint8_t *)(f + 9 * maxN);
     L.valid = b;
     L.ctrl = b + maxN;
-    return p + align_up((size_t)maxN * 38, 16);
+    L.infeas = b + 2 * maxN;
+    return p + align_up((size_t)maxN * 39, 16);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,7 +503,21 @@ __global__ __launch_bounds__(256) void k_dynamics(StepArgs A)
             }
             A.log_div[g] = d;
         }
+        if (A.infeasible) {
+            const bool both = valid && A.cur.valid[g];
+            A.infeasible[g] = both ? infeasible_transition(A.cur.vx[g], A.cur.vy[g], A.cur.yaw[g], vx, vy, A.dt) : 0;
+        }
     }
+}
+
+// Sparse reward of Sec. 5.2 from the step's masks: -1[collision] - 1[off-road].
+// One block per scenario (so one-scenario views of a batch stay in range).
+__global__ __launch_bounds__(256) void k_reward(const int32_t *__restrict__ obj_off, const uint8_t *__restrict__ col,
+                                                const uint8_t *__restrict__ off, float *__restrict__ reward)
+{
+    const int s = blockIdx.x;
+    for (int g = obj_off[s] + (int)threadIdx.x; g < obj_off[s + 1]; g += blockDim.x)
+        reward[g] = -(float)col[g] - (off ? (float)off[g] : 0.f);
 }
 
 __global__ __launch_bounds__(256) void k_inverse(int n, wm_state cur, wm_state nxt, float dt, float *__restrict__ accel,
@@ -411,15 +528,8 @@ __global__ __launch_bounds__(256) void k_inverse(int n, wm_state cur, wm_state n
         return;
     const bool ok = cur.valid[g] && nxt.valid[g];
     float a = 0.f, k = 0.f;
-    if (ok) {
-        const float vx = cur.vx[g], vy = cur.vy[g], nvx = nxt.vx[g], nvy = nxt.vy[g];
-        const float v = sqrtf(__builtin_fmaf(vy, vy, vx * vx));
-        const float nv = sqrtf(__builtin_fmaf(nvy, nvy, nvx * nvx));
-        a = (nv - v) / dt;
-        const float dist = __builtin_fmaf(v, dt, 0.5f * a * dt * dt);
-        const float heading = atan2f(nvy, nvx);
-        k = fabsf(dist) < 1e-6f ? 0.f : wrap_angle(heading - cur.yaw[g]) / dist;
-    }
+    if (ok)
+        inverse_kinematics(cur.vx[g], cur.vy[g], cur.yaw[g], nxt.vx[g], nxt.vy[g], dt, a, k);
     accel[g] = a;
     curv[g] = k;
     if (vout)
@@ -465,9 +575,8 @@ __global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
     ObjLds L;
     unsigned char *p = carve_objects(smem, 64 * A.CW, L);
     const int SL = 256 * A.CW;
-    float *sbest = (float *)p;
-    int *schunk = (int *)(sbest + A.G * SL);
-    float *sk = (float *)(schunk + A.G * SL);
+    const ScanLds C = carve_scan(p, A.G, SL);
+    float *sk = (float *)(p + scan_lds_bytes(A.G, A.CW));
     int *nidx = (int *)(sk + SL);
     const int s = blockIdx.x;
     const int o0 = __builtin_amdgcn_readfirstlane(A.obj_off[s]);
@@ -480,9 +589,10 @@ __global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
     for (int i = threadIdx.x; i < Ns; i += blockDim.x)
         load_object(L, i, A.st, o0 + i0 + i);
     __syncthreads();
-    const long eb = (long)__builtin_amdgcn_readfirstlane(A.rg_off[s]) + (long)s * kChunk;
-    const int nch = (__builtin_amdgcn_readfirstlane(A.ecount[s]) + kChunk - 1) / kChunk;
-    offroad_unit(L, 0, Ns, A.exy + eb, A.edir + eb, A.eidx + eb, nch, A.G, A.CW, sbest, schunk, sk, nidx);
+    const long eb = edge_base(__builtin_amdgcn_readfirstlane(A.rg_off[s]), s);
+    const int E = __builtin_amdgcn_readfirstlane(A.E.count[s]);
+    const float qqmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.E.qqmax[s])));
+    offroad_unit(L, 0, Ns, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb, E, qqmax, A.G, A.CW, C, sk, nidx);
     for (int il = threadIdx.x; il < Ns; il += blockDim.x) {
         float m = kNoValue;
         for (int k = 0; k < 4; ++k)
@@ -513,9 +623,8 @@ __global__ __launch_bounds__(512) void k_rollout(RollArgs A)
     const int SL = 256 * A.CW;
     const int nthr = blockDim.x;
     const int P = nthr / U;
-    float *sbest = (float *)p;
-    int *schunk = (int *)(sbest + A.G * SL);
-    float *sk = (float *)(schunk + A.G * SL);
+    const ScanLds C = carve_scan(p, A.G, SL);
+    float *sk = (float *)(p + scan_lds_bytes(A.G, A.CW));
     int *nidx = (int *)(sk + SL);
     float *red = (float *)(nidx + SL);
     float *wsum = red + nthr;
@@ -536,8 +645,9 @@ __global__ __launch_bounds__(512) void k_rollout(RollArgs A)
         const int o0 = __builtin_amdgcn_readfirstlane(A.obj_off[s]);
         const int N = __builtin_amdgcn_readfirstlane(A.obj_off[s + 1]) - o0;
         const int i0 = slice * U, Ns = min(U, N - i0);
-        const long eb = A.has_rg ? (long)__builtin_amdgcn_readfirstlane(A.rg_off[s]) + (long)s * kChunk : 0;
-        const int nch = A.has_rg ? (__builtin_amdgcn_readfirstlane(A.ecount[s]) + kChunk - 1) / kChunk : 0;
+        const long eb = A.has_rg ? edge_base(__builtin_amdgcn_readfirstlane(A.rg_off[s]), s) : 0;
+        const int E = A.has_rg ? __builtin_amdgcn_readfirstlane(A.E.count[s]) : 0;
+        const float qqmax = A.has_rg ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.E.qqmax[s]))) : 0.f;
         for (int i = tid; i < N; i += nthr) {
             load_object(L, i, A.init, o0 + i);
             L.ctrl[i] = A.act.controlled[o0 + i];
@@ -551,6 +661,8 @@ __global__ __launch_bounds__(512) void k_rollout(RollArgs A)
             const long row = (long)t * n, arow = (long)(t - 1) * n;
             for (int i = tid; i < N; i += nthr) {
                 const long g = o0 + i;
+                const float pvx = L.vx[i], pvy = L.vy[i], pyaw = L.yaw[i];
+                const bool pvalid = L.valid[i];
                 if (!L.ctrl[i]) {
                     load_object(L, i, A.log, row + g);
                 } else if (L.valid[i]) {
@@ -562,11 +674,15 @@ __global__ __launch_bounds__(512) void k_rollout(RollArgs A)
                     L.c[i] = cs;
                     L.s[i] = sn;
                 }
+                L.infeas[i] = (pvalid && L.valid[i]) ? infeasible_transition(pvx, pvy, pyaw, L.vx[i], L.vy[i], A.dt)
+                                                    : (uint8_t)0;
             }
             __syncthreads();
             for (int il = tid; il < Ns; il += nthr) {
                 const int i = i0 + il;
                 const long g = o0 + i;
+                if (A.met.infeasible)
+                    A.met.infeasible[arow + g] = L.infeas[i];
                 if (A.has_traj)
                     store_object(L, i, A.traj, arow + g);
                 if (A.has_ckpt && t % A.ckpt_every == 0 && t < A.T)
@@ -581,7 +697,7 @@ __global__ __launch_bounds__(512) void k_rollout(RollArgs A)
             }
             overlap_partial(L, N, i0, Ns, U, P, red, A.want_loss ? &my_loss : nullptr, nullptr, nullptr);
             if (A.has_rg) {
-                offroad_unit(L, i0, Ns, A.exy + eb, A.edir + eb, A.eidx + eb, nch, A.G, A.CW, sbest, schunk, sk,
+                offroad_unit(L, i0, Ns, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb, E, qqmax, A.G, A.CW, C, sk,
                              nidx);
             } else {
                 __syncthreads();
@@ -595,8 +711,8 @@ __global__ __launch_bounds__(512) void k_rollout(RollArgs A)
                     A.met.collision[g] = (uint8_t)(m > 0.f);
                 if (A.met.overlap_margin)
                     A.met.overlap_margin[g] = m;
+                float r = kNoValue;
                 if (A.has_rg) {
-                    float r = kNoValue;
                     for (int k = 0; k < 4; ++k)
                         r = fmaxf(r, sk[4 * il + k]);
                     if (A.met.offroad)
@@ -604,6 +720,8 @@ __global__ __launch_bounds__(512) void k_rollout(RollArgs A)
                     if (A.met.offroad_margin)
                         A.met.offroad_margin[g] = r;
                 }
+                if (A.met.reward)
+                    A.met.reward[g] = -(float)(m > 0.f) - (float)(r > 0.f);
             }
             __syncthreads();
         }
@@ -645,14 +763,12 @@ __global__ void k_loss_reduce(int S, const int32_t *__restrict__ uoff, const flo
 // ---------------------------------------------------------------------------
 namespace wm {
 
-static size_t objects_lds(int maxN) { return align_up((size_t)maxN * 38, 16); }
+static size_t objects_lds(int maxN) { return align_up((size_t)maxN * 39, 16); }
 
 void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned char *ws, const WsLayout &L,
                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_compact_edges<256>, dim3(b.num_scenarios), dim3(256), 0, st, b.rg_off, rg,
-                       (float2 *)(ws + L.exy), (float2 *)(ws + L.edir), (int32_t *)(ws + L.eidx),
-                       (int32_t *)(ws + L.ecount));
+    hipLaunchKernelGGL(k_compact_edges<256>, dim3(b.num_scenarios), dim3(256), 0, st, b.rg_off, rg, ws_edges(ws, L));
 }
 
 void launch_build_units(const wm_batch &b, int U, const int32_t *ecount, unsigned char *ws, const WsLayout &L,
@@ -665,6 +781,11 @@ void launch_build_units(const wm_batch &b, int U, const int32_t *ecount, unsigne
 void launch_dynamics(const wm_batch &b, const StepArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_dynamics, dim3(b.num_scenarios), dim3(128), 0, st, a);
+}
+
+void launch_reward(const wm_batch &b, const uint8_t *col, const uint8_t *off, float *reward, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reward, dim3(b.num_scenarios), dim3(256), 0, st, b.obj_off, col, off, reward);
 }
 
 void launch_inverse(int n, const wm_state &cur, const wm_state &nxt, float dt, float *accel, float *curv,
@@ -682,7 +803,7 @@ void launch_overlap(const wm_batch &b, const OverlapArgs &a, hipStream_t st)
     hipLaunchKernelGGL(k_overlap, dim3(b.num_scenarios, slices), dim3(256), lds, st, a);
 }
 
-static size_t offroad_scratch(int G, int CW) { return (size_t)G * 256 * CW * 8 + (size_t)256 * CW * 8; }
+static size_t offroad_scratch(int G, int CW) { return scan_lds_bytes(G, CW) + (size_t)256 * CW * 8; }
 
 void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
 {

@@ -47,7 +47,11 @@ class CAction(C.Structure):
 
 class CMetrics(C.Structure):
     _fields_ = [("collision", _P), ("offroad", _P), ("overlap_margin", _P), ("offroad_margin", _P),
-                ("log_div", _P)]
+                ("log_div", _P), ("infeasible", _P), ("reward", _P)]
+
+
+class CDeltaAction(C.Structure):
+    _fields_ = [("dx", _P), ("dy", _P), ("dyaw", _P), ("controlled", _P)]
 
 
 class CTuning(C.Structure):
@@ -91,6 +95,10 @@ def lib() -> C.CDLL:
         L.wm_rollout_backward.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction),
                                           C.POINTER(CState), C.c_int32, C.c_float, C.c_int32, C.POINTER(CState),
                                           _P, _P, _P, _P, C.c_size_t, _P]
+        L.wm_step_delta.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CDeltaAction),
+                                    C.POINTER(CState), C.c_float, C.POINTER(CState), _P]
+        L.wm_inverse_delta.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CState), _P, _P, _P, _P, _P]
+        L.wm_discretize.argtypes = [_P, C.c_int32, C.c_float, C.c_float, C.c_int32, _P, _P, _P]
         L.wm_profile_enable.argtypes = [C.c_int]
         L.wm_profile_collect.argtypes = [C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
         L.wm_autotune.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
@@ -228,16 +236,23 @@ class Metrics:
     overlap_margin: Optional[torch.Tensor] = None
     offroad_margin: Optional[torch.Tensor] = None
     log_div: Optional[torch.Tensor] = None
+    infeasible: Optional[torch.Tensor] = None
+    reward: Optional[torch.Tensor] = None
+
+    FIELDS = ("collision", "offroad", "overlap_margin", "offroad_margin", "log_div", "infeasible", "reward")
 
     @classmethod
     def empty(cls, shape, device) -> "Metrics":
         u8 = lambda: torch.empty(shape, dtype=torch.uint8, device=device)  # noqa: E731
         f32 = lambda: torch.empty(shape, dtype=torch.float32, device=device)  # noqa: E731
-        return cls(u8(), u8(), f32(), f32(), f32())
+        return cls(u8(), u8(), f32(), f32(), f32(), u8(), f32())
+
+    def row(self, t: int) -> "Metrics":
+        return Metrics(*[None if getattr(self, f) is None else getattr(self, f)[t] for f in self.FIELDS])
 
     def c(self) -> CMetrics:
         return CMetrics(_ptr(self.collision), _ptr(self.offroad), _ptr(self.overlap_margin),
-                        _ptr(self.offroad_margin), _ptr(self.log_div))
+                        _ptr(self.offroad_margin), _ptr(self.log_div), _ptr(self.infeasible), _ptr(self.reward))
 
 
 def _tune(t):
@@ -264,6 +279,26 @@ def inverse_action(batch: Batch, cur: State, nxt: State, dt: float, accel: torch
     b, c, n = batch.c(), cur.c(), nxt.c()
     _check(lib().wm_inverse_action(C.byref(b), C.byref(c), C.byref(n), dt, accel.data_ptr(), curvature.data_ptr(),
                                    _ptr(valid_out), _stream(stream)))
+
+
+def step_delta(batch: Batch, cur: State, dx: torch.Tensor, dy: torch.Tensor, dyaw: torch.Tensor,
+               controlled: torch.Tensor, log_next: State, dt: float, nxt: State, stream=None):
+    b, c, l, n = batch.c(), cur.c(), log_next.c(), nxt.c()
+    a = CDeltaAction(dx.data_ptr(), dy.data_ptr(), dyaw.data_ptr(), controlled.data_ptr())
+    _check(lib().wm_step_delta(C.byref(b), C.byref(c), C.byref(a), C.byref(l), dt, C.byref(n), _stream(stream)))
+
+
+def inverse_delta(batch: Batch, cur: State, nxt: State, dx: torch.Tensor, dy: torch.Tensor, dyaw: torch.Tensor,
+                  valid_out: Optional[torch.Tensor] = None, stream=None):
+    b, c, n = batch.c(), cur.c(), nxt.c()
+    _check(lib().wm_inverse_delta(C.byref(b), C.byref(c), C.byref(n), dx.data_ptr(), dy.data_ptr(), dyaw.data_ptr(),
+                                  _ptr(valid_out), _stream(stream)))
+
+
+def discretize(values: torch.Tensor, lo: float, hi: float, bins: int, index: torch.Tensor,
+               snapped: Optional[torch.Tensor] = None, stream=None):
+    _check(lib().wm_discretize(values.data_ptr(), values.numel(), lo, hi, bins, index.data_ptr(), _ptr(snapped),
+                               _stream(stream)))
 
 
 def overlap(batch: Batch, st: State, collision=None, max_margin=None, pair_off=None, margin=None, mask=None,

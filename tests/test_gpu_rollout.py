@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import (BAND, assert_state_close, compare_collision, compare_offroad, device, f64, within)
+from helpers import (assert_traj_close, compare_collision, compare_offroad, device, f64, scenario_band, state_delta,
+                     within)
 from paper_2310_08710_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -70,29 +71,39 @@ def test_fused_rollout_matches_oracle(seed):
     lw = sc.log_window()
     init = f64({k: v[0] for k, v in lw.items()})
     ref = oracle.rollout(sc.obj_off, sc.rg_off, init, sc.accel, sc.curvature, ctrl, f64(lw), f64(sc.rg), T, sc.dt)
-    # trajectory: float32 rounding accumulates over T steps; bound it by the
-    # per-step tolerance times the number of steps taken
-    for t in (0, T // 2, T - 1):
-        gt = {k: v[t] for k, v in g.items()}
-        ot = {k: v[t] for k, v in ref["traj"].items()}
-        assert_state_close(gt, ot, "traj t=%d" % t, atol=1e-5 * (t + 1), rtol=1e-4)
-    # metrics, teacher-forced: the oracle evaluates the GPU's own states
-    gm = {f: getattr(met, f).cpu().numpy() for f in ("collision", "offroad", "overlap_margin", "offroad_margin",
-                                                     "log_div")}
+    gm = {f: getattr(met, f).cpu().numpy() for f in METRICS}
+    compare_rollout(g, gm, loss.cpu().numpy(), ref, sc.obj_off, sc.rg_off, f64(sc.rg))
+
+
+METRICS = ("collision", "offroad", "overlap_margin", "offroad_margin", "log_div")
+
+
+def compare_rollout(g, gm, loss, ref, obj_off, rg_off, rg):
+    """GPU rollout outputs against the oracle's own rollout from the same
+    inputs (g: trajectory fields [T, n]; gm: metrics [T, n]; loss [S] or
+    None).  Trajectories: within 1e-4 of the scene scale at every step.
+    Metrics: margins within tolerance plus the Lipschitz band of the measured
+    state difference; masks bit-exact outside that band.  Returns the number
+    of near ties."""
+    T = g["x"].shape[0]
+    n = g["x"].shape[1]
     ties = 0
     for t in range(T):
-        st = f64({k: v[t] for k, v in g.items()})
-        o_col, o_mm, _ = oracle.overlap(sc.obj_off, st)
-        ties += compare_collision(gm["collision"][t], gm["overlap_margin"][t], o_col, o_mm, "t=%d" % t)
-        r = oracle.offroad(sc.obj_off, sc.rg_off, st, f64(sc.rg), band=BAND)
-        ties += compare_offroad(gm["offroad"][t], gm["offroad_margin"][t], r, "t=%d" % t)
-        lg = f64({k: v[t + 1] for k, v in lw.items()})
-        assert within(gm["log_div"][t], oracle.log_divergence(st, lg)).all()
-    assert ties <= T * n // 100
-    # loss, teacher-forced per step
-    o_loss = sum(oracle.state_loss(sc.obj_off, f64({k: v[t] for k, v in g.items()}),
-                                   f64({k: v[t + 1] for k, v in lw.items()}), ctrl) for t in range(T))
-    assert within(loss.cpu().numpy(), o_loss, atol=1e-3, rtol=1e-4).all()
+        gt = {k: v[t] for k, v in g.items()}
+        ot = {k: v[t] for k, v in ref["traj"].items()}
+        assert_traj_close(gt, ot, "t=%d" % t)
+        delta = state_delta(gt, ot)
+        band = scenario_band(delta, obj_off)
+        ties += compare_collision(gm["collision"][t], gm["overlap_margin"][t], ref["collision"][t],
+                                  ref["overlap_margin"][t], "t=%d" % t, band=band)
+        r = oracle.offroad(obj_off, rg_off, ot, rg, band=float(band.max()))
+        ties += compare_offroad(gm["offroad"][t], gm["offroad_margin"][t], r, "t=%d" % t, band=band)
+        ld = gm["log_div"][t]
+        assert (within(ld, ref["log_div"][t]) | (np.abs(ld - ref["log_div"][t]) <= delta + 1e-5)).all()
+    assert ties <= 2 * T * n // 50, (ties, T * n)
+    if loss is not None:
+        assert within(loss, ref["loss"], atol=1e-3, rtol=1e-3).all()
+    return ties
 
 
 def test_fused_equals_plain_and_all_tunings():
@@ -105,11 +116,11 @@ def test_fused_equals_plain_and_all_tunings():
     ptraj, pmet = _run_plain(ds, sc, dev)
     for f in synth.STATE_FIELDS + ("valid",):
         assert torch.equal(getattr(traj, f), getattr(ptraj, f)), f
-    for f in ("collision", "offroad", "overlap_margin", "offroad_margin", "log_div"):
+    for f in wm.Metrics.FIELDS:
         assert torch.equal(getattr(met, f), getattr(pmet, f)), f
     for tune in ((64, 1), (64, 2), (64, 8), (128, 2), (128, 4), (256, 2)):
         t2, m2, l2, _ = _run_fused(ds, sc, dev, tune=tune)
-        for f in ("collision", "offroad", "overlap_margin", "offroad_margin"):
+        for f in ("collision", "offroad", "overlap_margin", "offroad_margin", "infeasible", "reward"):
             assert torch.equal(getattr(m2, f), getattr(met, f)), (tune, f)
         assert torch.equal(t2.x, traj.x)
         # the loss partials depend on the slice size only through summation order

@@ -157,3 +157,32 @@ def test_delta_dynamics_inverse_identity():
     dx, dy, dyaw, v = oracle.delta_inverse(s, s1)
     np.testing.assert_allclose(np.stack([dx, dy, dyaw]), d, atol=1e-12)
     assert v.all()
+
+
+def test_infeasibility_thresholds():
+    # Sec. 3.4: |a| > 6 m/s^2 or |kappa| > 0.3 1/m from inverse kinematics.
+    # Transitions made by the bicycle model itself within the limits are
+    # feasible; just beyond either limit they are not.
+    rng = np.random.default_rng(6)
+    n = 400
+    yaw = rng.uniform(-math.pi, math.pi, n)
+    v = rng.uniform(2, 20, n)
+    s = _state(rng.uniform(-80, 80, n), rng.uniform(-80, 80, n), yaw, v * np.cos(yaw), v * np.sin(yaw))
+    ctrl = np.ones(n, np.uint8)
+    a = rng.uniform(-5.9, 5.9, n)
+    k = rng.uniform(-0.29, 0.29, n)
+    s1 = oracle.bicycle_forward(s, a, k, ctrl, s, DT)
+    assert not oracle.infeasibility(s, s1, DT).any()
+    for aa, kk, expect in ((6.1, 0.0, 1), (-6.1, 0.0, 1), (0.0, 0.31, 1), (0.0, -0.31, 1), (5.9, 0.29, 0)):
+        s2 = oracle.bicycle_forward(s, np.full(n, aa), np.full(n, kk), ctrl, s, DT)
+        assert (oracle.infeasibility(s, s2, DT) == expect).all(), (aa, kk)
+    s3 = dict(s1)
+    s3["valid"] = np.zeros(n, np.uint8)
+    s4 = oracle.bicycle_forward(s, np.full(n, 9.0), np.zeros(n), ctrl, s, DT)
+    assert not oracle.infeasibility(s, dict(s4, valid=s3["valid"]), DT).any()
+    # a delta-action jump of 0.5 rad in one 0.1 s step at 10 m/s is infeasible
+    d = oracle.delta_forward(_state([0.0], [0.0], [0.0], [10.0], [0.0]), [1.0], [0.0], [0.5], np.ones(1, np.uint8),
+                             _state([0.0], [0.0], [0.0], [0.0], [0.0]), DT)
+    d["vx"], d["vy"] = np.array([10 * math.cos(0.5)]), np.array([10 * math.sin(0.5)])
+    assert oracle.infeasibility(_state([0.0], [0.0], [0.0], [10.0], [0.0]), d, DT)[0] == 1
+    np.testing.assert_array_equal(oracle.reward([0, 1, 1, 0], [0, 0, 1, 1]), [0.0, -1.0, -2.0, -1.0])
