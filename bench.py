@@ -348,6 +348,97 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
                       "output_GBps": out_bytes / (okm * 1e-3) / 1e9}
     log("observe: %.3f ms for %d egos (kernel %.3f ms)" % (oms, S * E, okm))
 
+    ragged(out, dev)
+
+
+def _time_graph(fn, reps):
+    """Capture fn() as one HIP graph and return the mean wall time of a replay [ms]."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    del g
+    return ms
+
+
+def ragged(out, dev, T_cmp=10):
+    """Ragged batch (1,024 scenarios, objects U{8..128}, road points
+    U{2,000..30,000}): the fused persistent rollout (autotuned, HIP graph) over
+    80 steps, and fused against the plain one-scenario-per-launch form over the
+    first T_cmp steps (both as HIP graphs, identical outputs)."""
+    import torch
+    from paper_2310_08710_amd import synth, wm
+    sc = synth.make_scene(2)
+    ds = wm.upload(sc, dev)
+    n, T = sc.total_objects, sc.steps
+    valid = int(sc.log["valid"][synth.T0].sum())
+    ws = ds.batch.workspace(T, 0)
+    tune = wm.autotune(ds.batch, ds.init, ds.act_seq, ds.log_seq, ds.rg, T, sc.dt, ws)
+    met = wm.Metrics.empty((T, n), dev)
+    traj = wm.State.empty((T, n), dev)
+
+    def fused(steps):
+        wm.rollout(ds.batch, ds.init, ds.act_seq, ds.log_seq, ds.rg, steps, sc.dt, ws, traj=traj, metrics=met,
+                   tune=tune)
+
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_ROLLOUT)
+    fms = _time_graph(lambda: fused(T), 3)
+    kms, kl = wm.profile_collect(wm.PROF_ROLLOUT)
+    wm.profile_enable(False)
+    ops, _ = rollout_ops(sc, T)
+    kernel_ms = kms / max(kl, 1)
+    res = {"workload": "1024 ragged scenarios, objects U{8..128}, road points U{2000..30000}, 80 steps",
+           "tuning": list(tune), "fused_ms_per_rollout": fms, "value": valid * T / (fms * 1e-3),
+           "unit": "agent-steps/s", "kernel_ms": kernel_ms,
+           "roofline_frac": ops / (kernel_ms * 1e-3) / PEAK_FP32}
+    log("ragged fused: %.3f ms/rollout, %.3e agent-steps/s, kernel %.1f%% of FP32 peak" % (
+        fms, res["value"], 100 * res["roofline_frac"]))
+
+    # fused vs one launch sequence per scenario and step, first T_cmp steps
+    off = np.asarray(sc.obj_off)
+    counts = np.diff(off)
+    rgc = np.diff(np.asarray(sc.rg_off))
+    views = [wm.Batch(ds.batch.obj_off[s:s + 2], ds.batch.rg_off[s:s + 2], 1, n, ds.batch.total_rg_points,
+                      int(counts[s]), int(rgc[s])) for s in range(sc.num_scenarios)]
+    wsv = views[int(np.argmax(rgc))].workspace()
+    ptraj = wm.State.empty((T_cmp, n), dev)
+    pmet = wm.Metrics.empty((T_cmp, n), dev)
+    acts = [wm.Action(ds.act_seq.accel[t], ds.act_seq.curvature[t], ds.act_seq.controlled) for t in range(T_cmp)]
+    logs = [ds.log_seq.row(t + 1) for t in range(T_cmp)]
+    rows = [ptraj.row(t) for t in range(T_cmp)]
+    mets = [pmet.row(t) for t in range(T_cmp)]
+
+    def plain():
+        for v in views:
+            c = ds.init
+            for t in range(T_cmp):
+                wm.step(v, c, acts[t], logs[t], ds.rg, sc.dt, rows[t], mets[t], wsv)
+                c = rows[t]
+
+    pms = _time_graph(plain, 2)
+    f10 = _time_graph(lambda: fused(T_cmp), 5)
+    same = all(torch.equal(getattr(met, f)[:T_cmp], getattr(pmet, f)) for f in wm.Metrics.FIELDS) and \
+        torch.equal(traj.x[:T_cmp], ptraj.x)
+    res.update({"steps_compared": T_cmp, "fused_ms": f10, "per_scenario_plain_ms": pms,
+                "per_scenario_launches": int(sc.num_scenarios * T_cmp), "fused_speedup": pms / f10,
+                "identical_outputs": bool(same)})
+    log("ragged %d steps: fused %.3f ms vs per-scenario plain %.3f ms (%.1fx), identical=%s" % (
+        T_cmp, f10, pms, pms / f10, same))
+    out["ragged"] = res
+
 
 if __name__ == "__main__":
     main()

@@ -130,7 +130,9 @@ typedef struct wm_metrics {
  * library's choice (autotuned table if wm_autotune has run, else a default).
  *   unit_objects  objects per work unit (one work-group): 64, 128 or 256
  *   edge_splits   road-edge ranges scanned in parallel per object: 1, 2, 4, 8 or 16
- * unit_objects * edge_splits must not exceed 1024. */
+ * unit_objects * edge_splits (the work-group size) must not exceed 1024 for
+ * wm_offroad and 512 for wm_rollout / wm_autotune; larger values fail with
+ * WM_ERR_RANGE. */
 typedef struct wm_tuning {
     int32_t unit_objects;
     int32_t edge_splits;

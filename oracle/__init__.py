@@ -202,18 +202,20 @@ def overlap(obj_off, state, matrix: bool = False):
 def offroad(obj_off, rg_off, state, rg, band: float = 1e-4):
     """Off-road metric, Sec. 3.4.  Returns dict with per-object 'offroad',
     'margin' and per-corner 'nearest' (scenario-local index), 'corner_margin',
-    'ambiguous' ([n, 4])."""
+    'ambiguous' (another point within `band` of the nearest distance lies on
+    the other side, or |margin| < band) and 'tied' (another point within
+    `band` of the nearest distance at all), each [n, 4]."""
     off, roff = _i32(obj_off), _i32(rg_off)
     S = off.shape[0] - 1
     st, g = OState(state), ORoadgraph(rg)
     n = int(off[-1])
     out = {"offroad": np.zeros(n, np.uint8), "margin": np.zeros(n),
            "nearest": np.zeros((n, 4), np.int32), "corner_margin": np.zeros((n, 4)),
-           "ambiguous": np.zeros((n, 4), np.uint8)}
+           "ambiguous": np.zeros((n, 4), np.uint8), "tied": np.zeros((n, 4), np.uint8)}
     lib().or_offroad(C.c_int(S), _p(off, C.c_int32), _p(roff, C.c_int32), C.byref(st.c), C.byref(g.c),
                      C.c_double(band), _p(out["margin"], C.c_double), _p(out["offroad"], C.c_uint8),
                      _p(out["nearest"], C.c_int32), _p(out["corner_margin"], C.c_double),
-                     _p(out["ambiguous"], C.c_uint8))
+                     _p(out["ambiguous"], C.c_uint8), _p(out["tied"], C.c_uint8))
     return out
 
 

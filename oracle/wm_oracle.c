@@ -335,11 +335,14 @@ void or_overlap(int S, const int32_t *obj_off, const or_state *st,
  *    edge point the margin is -FLT_MAX and the object is on the road.
  * Near-tie report: a corner is ambiguous when |s| < band, or when another
  * edge point lies within `band` metres of the nearest distance and falls on
- * the other side.  `nearest` holds scenario-local point indices (-1: none).
+ * the other side (the mask may flip); it is tied when another edge point lies
+ * within `band` metres of the nearest distance at all (the nearest index and
+ * the margin may change, the side need not).  `nearest` holds scenario-local
+ * point indices (-1: none).
  * ---------------------------------------------------------------------- */
 void or_offroad(int S, const int32_t *obj_off, const int32_t *rg_off, const or_state *st,
                 const or_roadgraph *rg, double band, double *margin, uint8_t *offroad,
-                int32_t *nearest, double *corner_margin, uint8_t *corner_ambiguous)
+                int32_t *nearest, double *corner_margin, uint8_t *corner_ambiguous, uint8_t *corner_tied)
 {
     static const double sl[4] = {1.0, 1.0, -1.0, -1.0};
     static const double sw[4] = {1.0, -1.0, -1.0, 1.0};
@@ -350,7 +353,7 @@ void or_offroad(int S, const int32_t *obj_off, const int32_t *rg_off, const or_s
             for (int k = 0; k < 4; ++k) {
                 int q = -1;
                 double qd = 0.0, sk = OR_NO_VALUE;
-                int amb = 0;
+                int amb = 0, tied = 0;
                 if (st->valid[i]) {
                     double c = cos(st->yaw[i]), sn = sin(st->yaw[i]);
                     double hl = 0.5 * st->length[i], hw = 0.5 * st->width[i];
@@ -370,13 +373,14 @@ void or_offroad(int S, const int32_t *obj_off, const int32_t *rg_off, const or_s
                         int g = p0 + q;
                         sk = -(rg->dir_x[g] * (cy - rg->y[g]) - rg->dir_y[g] * (cx - rg->x[g]));
                         amb = fabs(sk) < band;
-                        for (int j = 0; j < P && !amb; ++j) {
+                        for (int j = 0; j < P && !(amb && tied); ++j) {
                             int h = p0 + j;
                             if (j == q || !rg->valid[h] || rg->type[h] != OR_ROAD_EDGE)
                                 continue;
                             double d = sqrt((cx - rg->x[h]) * (cx - rg->x[h]) + (cy - rg->y[h]) * (cy - rg->y[h]));
                             if (d <= qd + band) {
                                 double sj = -(rg->dir_x[h] * (cy - rg->y[h]) - rg->dir_y[h] * (cx - rg->x[h]));
+                                tied = 1;
                                 if ((sj > 0.0) != (sk > 0.0))
                                     amb = 1;
                             }
@@ -389,6 +393,8 @@ void or_offroad(int S, const int32_t *obj_off, const int32_t *rg_off, const or_s
                     corner_margin[4L * i + k] = sk;
                 if (corner_ambiguous)
                     corner_ambiguous[4L * i + k] = (uint8_t)amb;
+                if (corner_tied)
+                    corner_tied[4L * i + k] = (uint8_t)tied;
                 if (sk > best_margin)
                     best_margin = sk;
             }
@@ -601,7 +607,7 @@ void or_rollout(int S, const int32_t *obj_off, const int32_t *rg_off, const or_s
                    overlap_margin ? overlap_margin + row : NULL);
         if (rg && (offroad || offroad_margin))
             or_offroad(S, obj_off, rg_off, nxt, rg, 0.0, offroad_margin ? offroad_margin + row : NULL,
-                       offroad ? offroad + row : NULL, NULL, NULL, NULL);
+                       offroad ? offroad + row : NULL, NULL, NULL, NULL, NULL);
         if (log_div)
             or_log_divergence((int)n, nxt, &lg, log_div + row);
         if (loss)

@@ -120,7 +120,8 @@ std::pair<int, int> tune_key(const wm_batch *b)
     return {ob, pb};
 }
 
-int resolve_tune(const wm_batch *b, const wm_tuning *t, Tune *out)
+// max_threads is the work-group size limit of the kernel the tuning is for.
+int resolve_tune(const wm_batch *b, const wm_tuning *t, int max_threads, Tune *out)
 {
     if (t) {
         const int U = t->unit_objects, G = t->edge_splits;
@@ -128,8 +129,8 @@ int resolve_tune(const wm_batch *b, const wm_tuning *t, Tune *out)
             return fail(WM_ERR_RANGE, "unit_objects = %d not in {64, 128, 256}", U);
         if (G != 1 && G != 2 && G != 4 && G != 8 && G != 16)
             return fail(WM_ERR_RANGE, "edge_splits = %d not in {1, 2, 4, 8, 16}", G);
-        if (U * G > 1024)
-            return fail(WM_ERR_RANGE, "unit_objects * edge_splits = %d > 1024", U * G);
+        if (U * G > max_threads)
+            return fail(WM_ERR_RANGE, "unit_objects * edge_splits = %d > %d", U * G, max_threads);
         out->G = G;
         out->CW = U / 64;
         return WM_OK;
@@ -296,7 +297,7 @@ int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, co
     if (want_off) {
         unsigned char *w = (unsigned char *)ws;
         Tune tn;
-        CHECK(resolve_tune(batch, nullptr, &tn));
+        CHECK(resolve_tune(batch, nullptr, 1024, &tn));
         tn.CW = 1;
         if (tn.G > 16)
             tn.G = 16;
@@ -395,7 +396,7 @@ int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
         return fail(WM_ERR_NULL, "roadgraph is NULL");
     CHECK(check_rg(rg));
     Tune tn;
-    CHECK(resolve_tune(batch, tune, &tn));
+    CHECK(resolve_tune(batch, tune, 1024, &tn));
     const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
     CHECK(check_ws(ws, ws_bytes, L.total));
     if (!offroad && !margin && !nearest_idx)
@@ -471,7 +472,7 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
     if (traj)
         CHECK(check_state(traj, "traj"));
     Tune tn;
-    CHECK(resolve_tune(batch, tune, &tn));
+    CHECK(resolve_tune(batch, tune, 512, &tn));
     const wm::WsLayout L =
         wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, T, ckpt_every);
     CHECK(check_ws(ws, ws_bytes, L.total));
@@ -568,7 +569,7 @@ int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *ac
     CHECK(rollout_checks(batch, init, act_seq, log_seq, T, dt, 0));
     const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, T, 0);
     CHECK(check_ws(ws, ws_bytes, L.total));
-    static const int cand[][2] = {{64, 2}, {64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8}, {256, 2}, {256, 4}};
+    static const int cand[][2] = {{64, 2}, {64, 4}, {64, 8}, {128, 1}, {128, 2}, {128, 4}, {256, 1}, {256, 2}};
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

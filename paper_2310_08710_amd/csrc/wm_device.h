@@ -200,42 +200,83 @@ __device__ __forceinline__ float candidate_band(float qqmax, float cx, float cy)
     return 0x1p-19f * r * r;
 }
 
+// Bytes of the per-wave LDS stage of the scan (one chunk).
+constexpr int kStageBytes = kChunkFloats * 4;
+
+// Minimum of T over one chunk already staged in LDS (x, y, qq columns),
+// folded into m.  All lanes read the same addresses (LDS broadcast reads of
+// four points per column); the points are VGPR operands of the FMAs.
 template <int R>
-__device__ __forceinline__ void scan_edges(const float *__restrict__ stream, int c0, int c1, const float (&cx)[R],
-                                           const float (&cy)[R], float (&b1)[R], float (&b2)[R], float (&b3)[R],
-                                           int (&i1)[R], int (&i2)[R])
+__device__ __forceinline__ void fold_chunk(const float4 *stage, const float (&m2x)[R],
+                                           const float (&m2y)[R], float (&m)[R])
 {
-    c0 = __builtin_amdgcn_readfirstlane(c0);
-    c1 = __builtin_amdgcn_readfirstlane(c1);
+#pragma unroll 4
+    for (int j4 = 0; j4 < kChunk / 4; ++j4) {
+        const float4 X = stage[j4], Y = stage[kChunk / 4 + j4], Q = stage[kChunk / 2 + j4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float t0 = __builtin_fmaf(m2y[r], Y.x, __builtin_fmaf(m2x[r], X.x, Q.x));
+            const float t1 = __builtin_fmaf(m2y[r], Y.y, __builtin_fmaf(m2x[r], X.y, Q.y));
+            const float t2 = __builtin_fmaf(m2y[r], Y.z, __builtin_fmaf(m2x[r], X.z, Q.z));
+            const float t3 = __builtin_fmaf(m2y[r], Y.w, __builtin_fmaf(m2x[r], X.w, Q.w));
+            m[r] = fminf(fminf(m[r], t0), t1);
+            m[r] = fminf(fminf(m[r], t2), t3);
+        }
+    }
+}
+
+// Scan of chunks [c0, c1) by one wave for R corner sets per lane.  The wave
+// stages each chunk through its own LDS stage (`stage`, kStageBytes): every
+// lane fetches its 16-byte pieces of the next chunk into registers while the
+// current one is folded (global loads complete in order, so the fetch stays
+// in flight), then writes them to the stage once the current chunk has been
+// read, and all lanes read the chunk back as broadcasts.  A wave's LDS
+// operations execute in order, so one stage suffices.  Keeps per corner the
+// three smallest chunk minima and the chunks of the first two.
+template <int R>
+__device__ __forceinline__ void scan_edges(const float *__restrict__ stream, int c0, int c1, float4 *stage,
+                                           const float (&cx)[R], const float (&cy)[R], float (&b1)[R],
+                                           float (&b2)[R], float (&b3)[R], int (&i1)[R], int (&i2)[R])
+{
     if (c0 >= c1)
         return;
-    uniform_fptr e = (uniform_fptr)stream;
+    constexpr int kC4 = kStageBytes / 16;             // float4 per chunk
+    static_assert(kC4 > 64 && kC4 <= 128, "two 16-byte pieces per lane");
+    const int lane = threadIdx.x & 63;
+    const bool second = lane < kC4 - 64;
+    const float4 *src = (const float4 *)stream + lane;
     float m2x[R], m2y[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         m2x[r] = -2.0f * cx[r];
         m2y[r] = -2.0f * cy[r];
     }
+    float4 va = src[(long)kC4 * c0], vb = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (second)
+        vb = src[(long)kC4 * c0 + 64];
     for (int c = c0; c < c1; ++c) {
+        stage[lane] = va;
+        if (second)
+            stage[64 + lane] = vb;
+        if (c + 1 < c1) {
+            va = src[(long)kC4 * (c + 1)];
+            if (second)
+                vb = src[(long)kC4 * (c + 1) + 64];
+        }
         float m[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
             m[r] = __builtin_inff();
-        uniform_fptr p = e + kChunkFloats * c;
-#pragma unroll 16
-        for (int j = 0; j < kChunk; ++j) {
-            const float qx = p[j], qy = p[kChunk + j], qq = p[2 * kChunk + j];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                m[r] = fminf(m[r], __builtin_fmaf(m2y[r], qy, __builtin_fmaf(m2x[r], qx, qq)));
-        }
+        fold_chunk<R>(stage, m2x, m2y, m);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            // selects on the two comparisons keep the update branch-free
             const bool lt1 = m[r] < b1[r], lt2 = m[r] < b2[r];
             b3[r] = __builtin_amdgcn_fmed3f(b2[r], b3[r], m[r]);
             b2[r] = __builtin_amdgcn_fmed3f(b1[r], b2[r], m[r]);
-            b1[r] = fminf(b1[r], m[r]);
-            i2[r] = lt1 ? i1[r] : (lt2 ? c : i2[r]);
+            b1[r] = lt1 ? m[r] : b1[r];
+            const int j2 = lt2 ? c : i2[r];
+            i2[r] = lt1 ? i1[r] : j2;
             i1[r] = lt1 ? c : i1[r];
         }
     }
@@ -269,21 +310,23 @@ __device__ __forceinline__ void rescan_chunk(const float *__restrict__ stream, i
 }
 
 // Exact scan of every chunk for one corner by a whole wave (the corner is
-// wave-uniform): lane l takes point l of each chunk, then a wave reduction on
-// (D, index) keeps the lowest index of the minimum.  Returns the point index
-// (or -1) in every lane.
+// wave-uniform): lane l takes points l, l + 64, ... of each chunk, then a
+// wave reduction on (D, index) keeps the lowest index of the minimum.
+// Returns the point index (or -1) in every lane.
 __device__ __forceinline__ int wave_full_scan(const float *__restrict__ stream, int nch, int E, float cx, float cy)
 {
     const int lane = threadIdx.x & 63;
     float best = __builtin_inff();
     int bj = 0x7fffffff;
     for (int c = 0; c < nch; ++c) {
-        const int j = kChunk * c + lane;
         const float *p = stream + kChunkFloats * c;
-        const float d = edge_d2(p[lane], p[kChunk + lane], cx, cy);
-        if (j < E && d < best) {
-            best = d;
-            bj = j;
+        for (int h = lane; h < kChunk; h += 64) {
+            const int j = kChunk * c + h;
+            const float d = edge_d2(p[h], p[kChunk + h], cx, cy);
+            if (j < E && d < best) {
+                best = d;
+                bj = j;
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) {

@@ -13,10 +13,10 @@ namespace wm {
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Road-edge points per chunk of the off-road scan.
-constexpr int kEdgeChunk = 64;
+constexpr int kEdgeChunk = 128;
 
 // First point slot of scenario s in the compacted road-edge arrays: a whole
-// number of chunks, at least P_s + 64 slots before the next scenario's.
+// number of chunks, at least P_s + kEdgeChunk slots before the next scenario's.
 __host__ __device__ inline long edge_base(int rg_off_s, int s)
 {
     return (long)kEdgeChunk * ((long)rg_off_s / kEdgeChunk + 2L * s);
@@ -26,7 +26,7 @@ __host__ __device__ inline long edge_base(int rg_off_s, int s)
 // from edge_base(rg_off[s], s): its valid road edges in index order, padded
 // to whole chunks (two spare chunks at the end of the arrays let the scan
 // prefetch past the last chunk).  `stream` holds chunk c
-// of that range as x[64], y[64], qq[64] (qq = x^2 + y^2; padding points have
+// of that range as x[128], y[128], qq[128] (qq = x^2 + y^2; padding points have
 // x = y = 0 and qq = +inf); `dir` and `idx` (scenario-local original index)
 // are indexed by point.  `count` = edges per scenario, `qqmax` = their max qq.
 struct Edges {

@@ -25,7 +25,7 @@ namespace wm {
 // ---------------------------------------------------------------------------
 // Road-edge compaction into the workspace stream (layout in wm_internal.h,
 // struct Edges): the valid road edges of scenario s in index order, chunked
-// as x[64] y[64] qq[64], plus their directions, original indices, count and
+// as x[], y[], qq[] columns of kEdgeChunk points, plus their directions, original indices, count and
 // the largest qq (it bounds the rounding of the scan's expanded distance).
 // ---------------------------------------------------------------------------
 template <int BT>
@@ -254,24 +254,31 @@ __device__ __forceinline__ void overlap_partial(const ObjLds &L, int N, int i0, 
 // Per-split candidate lists of the off-road scan in LDS: for every split g
 // and corner slot, the three smallest chunk minima and the first two chunks.
 struct ScanLds {
+    float4 *stage;  // one chunk stage per wave (kStageBytes each)
     float *b1, *b2, *b3;
     int *i1, *i2;
     int *full;      // corner slots that need the exact scan of every chunk
     int *nfull;
 };
 
+// p must be 16-byte aligned; waves = G * SL / 256.
 __device__ __forceinline__ ScanLds carve_scan(void *p, int G, int SL)
 {
-    float *f = (float *)p;
+    float4 *stage = (float4 *)p;
+    float *f = (float *)((unsigned char *)p + (size_t)kStageBytes * (G * SL / 256));
     const int m = G * SL;
     int *fl = (int *)(f + 5 * m);
-    return ScanLds{f, f + m, f + 2 * m, (int *)(f + 3 * m), (int *)(f + 4 * m), fl, fl + SL};
+    return ScanLds{stage, f, f + m, f + 2 * m, (int *)(f + 3 * m), (int *)(f + 4 * m), fl, fl + SL};
 }
 
-constexpr size_t scan_lds_bytes(int G, int CW) { return (size_t)G * 256 * CW * 20 + (size_t)256 * CW * 4 + 16; }
+constexpr size_t scan_lds_bytes(int G, int CW)
+{
+    return (size_t)kStageBytes * G * CW + (size_t)G * 256 * CW * 20 + (size_t)256 * CW * 4 + 16;
+}
 
 template <int R>
-__device__ __forceinline__ void scan_r(const float *stream, int c0, int c1, const float (&cx)[4], const float (&cy)[4],
+__device__ __forceinline__ void scan_r(const float *stream, int c0, int c1, float4 *stage, const float (&cx)[4],
+                                       const float (&cy)[4],
                                        float (&b1)[4], float (&b2)[4], float (&b3)[4], int (&i1)[4], int (&i2)[4])
 {
     float x[R], y[R], v1[R], v2[R], v3[R];
@@ -280,7 +287,7 @@ __device__ __forceinline__ void scan_r(const float *stream, int c0, int c1, cons
     for (int r = 0; r < R; ++r) {
         x[r] = cx[r]; y[r] = cy[r]; v1[r] = b1[r]; v2[r] = b2[r]; v3[r] = b3[r]; j1[r] = i1[r]; j2[r] = i2[r];
     }
-    scan_edges<R>(stream, c0, c1, x, y, v1, v2, v3, j1, j2);
+    scan_edges<R>(stream, c0, c1, stage, x, y, v1, v2, v3, j1, j2);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         b1[r] = v1[r]; b2[r] = v2[r]; b3[r] = v3[r]; i1[r] = j1[r]; i2[r] = j2[r];
@@ -323,14 +330,15 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
     }
     if (tid == 0)
         *C.nfull = 0;
+    float4 *stage = C.stage + (long)w * (kStageBytes / 16);
     if (Reff == 4)
-        scan_r<4>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
+        scan_r<4>(stream, c0, c1, stage, cx, cy, b1, b2, b3, i1, i2);
     else if (Reff == 3)
-        scan_r<3>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
+        scan_r<3>(stream, c0, c1, stage, cx, cy, b1, b2, b3, i1, i2);
     else if (Reff == 2)
-        scan_r<2>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
+        scan_r<2>(stream, c0, c1, stage, cx, cy, b1, b2, b3, i1, i2);
     else if (Reff == 1)
-        scan_r<1>(stream, c0, c1, cx, cy, b1, b2, b3, i1, i2);
+        scan_r<1>(stream, c0, c1, stage, cx, cy, b1, b2, b3, i1, i2);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int slot = base + lane + 64 * r;
@@ -614,7 +622,7 @@ __global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
 // all N_s objects (needed by the slice's pairs), then for the slice objects
 // the overlap, off-road, log divergence, loss terms, outputs and checkpoints.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_rollout(RollArgs A)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_rollout(RollArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     ObjLds L;

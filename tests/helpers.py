@@ -69,14 +69,16 @@ def offroad_decisive(ref, band=BAND):
 
 def compare_offroad(g_mask, g_margin, ref, where="", band=BAND):
     """Masks bit-exact on decisive objects; margins within tolerance (plus the
-    band when the states differ) on objects whose corners are unambiguous.
-    Returns the near-tie count."""
+    band when the states differ) on objects whose corners have a unique
+    nearest point (no other point within the band of its distance: float32
+    cannot order distances closer than its rounding at the scene's scale, and
+    the margin depends on which point is taken).  Returns the near-tie count."""
     dec = offroad_decisive(ref, band)
     exp = (dec > 0).astype(np.uint8)
     sel = dec != 0
     bad = np.flatnonzero(sel & (g_mask != exp))
     assert bad.size == 0, "%s offroad mask mismatches at %s" % (where, bad[:10])
-    clean = ~ref["ambiguous"].astype(bool).any(axis=1)
+    clean = ~(ref["ambiguous"].astype(bool) | ref["tied"].astype(bool)).any(axis=1)
     extra = np.broadcast_to(np.asarray(band, np.float64) - BAND, ref["margin"].shape)
     ok = within(g_margin, ref["margin"]) | (np.abs(g_margin - ref["margin"]) <= extra + ATOL) | ~clean
     bad = np.flatnonzero(~ok)

@@ -125,6 +125,9 @@ def test_fused_equals_plain_and_all_tunings():
         assert torch.equal(t2.x, traj.x)
         # the loss partials depend on the slice size only through summation order
         assert torch.allclose(l2, loss, rtol=1e-5, atol=1e-4)
+    # a work-group larger than the fused kernel allows is refused before launch
+    with pytest.raises(wm.WMError):
+        _run_fused(ds, sc, dev, tune=(256, 4))
     # two identical runs are bitwise identical
     t3, m3, l3, _ = _run_fused(ds, sc, dev)
     assert torch.equal(l3, loss) and torch.equal(m3.offroad_margin, met.offroad_margin)

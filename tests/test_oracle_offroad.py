@@ -124,6 +124,27 @@ def test_exact_tie_goes_to_lowest_index():
     r2 = oracle.offroad(off, roff, objs, _rg([pts[1], pts[0], pts[2]], dirs))
     assert r2["nearest"][0, 0] == 0 and r2["corner_margin"][0, 0] == -4.0
     assert r["ambiguous"][0, 0] == 1 and r2["ambiguous"][0, 0] == 1
+    assert r["tied"][0, 0] == 1 and r2["tied"][0, 0] == 1
+
+
+def test_same_side_tie_is_tied_not_ambiguous():
+    # two points at distance 5 from the front-left corner (2, 1), both above
+    # it with direction +x: same side, so the mask is decided (s = 4 for
+    # either) but the nearest index (lowest wins) is a tie
+    fl = (2.0, 1.0)
+    pts = [(fl[0] + 3, fl[1] + 4), (fl[0] - 3, fl[1] + 4), (50.0, 50.0)]
+    dirs = [(1.0, 0.0)] * 3
+    objs = _objs([0.0], [0.0], [0.0], [4.0], [2.0])
+    off, roff = np.array([0, 1], np.int32), np.array([0, 3], np.int32)
+    r = oracle.offroad(off, roff, objs, _rg(pts, dirs))
+    assert r["nearest"][0, 0] == 0 and r["corner_margin"][0, 0] == 4.0
+    assert r["ambiguous"][0, 0] == 0 and r["tied"][0, 0] == 1
+    # moved 1 cm closer to point 1: unique beyond a 1 mm band, tied within 5 cm
+    objs2 = _objs([-0.006], [0.008], [0.0], [4.0], [2.0])
+    r = oracle.offroad(off, roff, objs2, _rg(pts, dirs), band=1e-3)
+    assert r["nearest"][0, 0] == 1 and r["tied"][0, 0] == 0
+    r = oracle.offroad(off, roff, objs2, _rg(pts, dirs), band=5e-2)
+    assert r["tied"][0, 0] == 1
 
 
 def test_filters_type_validity_and_empty():
