@@ -349,6 +349,32 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
     log("observe: %.3f ms for %d egos (kernel %.3f ms)" % (oms, S * E, okm))
 
     ragged(out, dev)
+    idm(out, scene, ds, dev, tune)
+
+
+def idm(out, scene, ds, dev, tune):
+    """The same 256 x 128 batch with 8 controlled objects per scenario and the
+    other 120 as IDM sim agents (Sec. 3.5) against log playback of the same
+    objects, both fused rollouts of 80 steps with every metric."""
+    import torch
+    from paper_2310_08710_amd import wm
+    n, T = scene.total_objects, scene.steps
+    ctrl = torch.zeros(n, dtype=torch.uint8, device=dev)
+    off = np.asarray(scene.obj_off)
+    for s in range(scene.num_scenarios):
+        ctrl[int(off[s]):int(off[s]) + 8] = 1
+    act = wm.Action(ds.act_seq.accel, ds.act_seq.curvature, ctrl)
+    ws = ds.batch.workspace(T, 0)
+    traj = wm.State.empty((T, n), dev)
+    met = wm.Metrics.empty((T, n), dev)
+    ims = _time_graph(lambda: wm.rollout_idm(ds.batch, ds.init, act, ds.log_seq, ds.rg, T, scene.dt, ws, traj=traj,
+                                             metrics=met, tune=tune), 3)
+    pms = _time_graph(lambda: wm.rollout(ds.batch, ds.init, act, ds.log_seq, ds.rg, T, scene.dt, ws, traj=traj,
+                                         metrics=met, tune=tune), 3)
+    out["idm"] = {"ms_per_rollout": ims, "value": n * T / (ims * 1e-3), "unit": "agent-steps/s",
+                  "playback_ms_per_rollout": pms, "agents_per_scenario": 120,
+                  "parameters": dict(wm.IDM_DEFAULT)}
+    log("IDM rollout: %.3f ms (playback of the same objects %.3f ms)" % (ims, pms))
 
 
 def _time_graph(fn, reps):

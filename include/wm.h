@@ -60,6 +60,7 @@ extern "C" {
 #define WM_MAX_OBJECTS 1024      /* objects per scenario */
 #define WM_MAX_TOPK 1024         /* k of wm_observe */
 #define WM_MAX_OBSERVE_POINTS 32768 /* road points per scenario for wm_observe */
+#define WM_MAX_IDM_POSES 64      /* lookahead poses of wm_rollout_idm */
 
 /* Road-point type of an oriented road edge (Sec. 3.4, Off-Road). */
 #define WM_TYPE_ROAD_EDGE 1
@@ -247,6 +248,47 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
                const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, int32_t ckpt_every,
                wm_state *ckpt, wm_state *traj, wm_metrics *met_seq, float *loss, const wm_tuning *tune,
                void *ws, size_t ws_bytes, void *stream);
+
+/* IDM sim agents (Sec. 3.5, simulated agent behaviour; intelligent driver
+ * model of Treiber, Hennecke and Helbing 2000).  Field units: m, s. */
+typedef struct wm_idm {
+    float desired_speed;   /* v0 */
+    float min_gap;         /* s0 */
+    float time_headway;    /* T_h */
+    float max_accel;       /* a_max */
+    float comfort_decel;   /* b */
+    float exponent;        /* delta */
+    float max_brake;       /* hardest deceleration (> 0); also the response to a zero gap */
+    float lookahead_step;  /* spacing of the lookahead poses along the path (> 0) */
+    int32_t lookahead_poses; /* 1..WM_MAX_IDM_POSES */
+} wm_idm;
+
+/* Fused rollout as wm_rollout (no checkpoints, no loss) in which every
+ * uncontrolled object whose log is valid in all rows 0..T is an IDM agent;
+ * other uncontrolled objects replay the log, controlled ones follow act_seq.
+ * An agent follows the polyline of its logged positions (rows 0..T, arc
+ * length from row 0) with progress sigma (0 at t = 0).  Each step, with all
+ * objects at time t-1:
+ *   lead: lookahead poses at sigma + m * step (m = 1..poses, up to the path
+ *     end) carry the agent's box; the lead is the valid object whose box
+ *     overlaps (separating-axis margin > 0) the pose with the smallest m, then
+ *     the lowest index; gap = (m - 1) * step; v_lead = its velocity along the
+ *     agent's yaw.
+ *   a = a_max (1 - (v / v0)^delta - (s_star / gap)^2), s_star = s0 +
+ *     max(0, v T_h + v (v - v_lead) / (2 sqrt(a_max b))), no interaction
+ *     term without a lead, -max_brake at gap 0, clamped to
+ *     [-max_brake, a_max].
+ *   v' = v + a dt, sigma += v dt + a dt^2 / 2 (or v^2 / (2|a|) and v' = 0 when
+ *     stopping within the step); an agent reaching the path end halts there
+ *     (sigma = path length, v' = 0); the pose at
+ *     sigma: position interpolated linearly between logged rows, yaw between
+ *     their yaws along the shorter arc; velocity v' along that yaw; length,
+ *     width and valid from log row t.
+ * Metrics as wm_rollout.  Workspace: wm_workspace_bytes(batch, T, 0). */
+int wm_rollout_idm(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
+                   const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, const wm_idm *idm,
+                   wm_state *traj, wm_metrics *met_seq, const wm_tuning *tune, void *ws, size_t ws_bytes,
+                   void *stream);
 
 /* Adjoint of wm_rollout's loss with respect to the actions (differentiable
  * simulation, Sec. 1 / Sec. 6), by a hand-written reverse sweep that

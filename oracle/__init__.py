@@ -273,6 +273,51 @@ def rollout(obj_off, rg_off, init, accel, curvature, controlled, log_seq, rg, T:
     return out
 
 
+# IDM sim-agent parameters (Sec. 3.5; values are readings, the paper gives
+# none): desired speed v0 [m/s], minimum gap s0 [m], time headway [s],
+# maximum acceleration and comfortable deceleration [m/s^2], exponent,
+# hardest braking [m/s^2], lookahead pose spacing [m] and pose count.
+IDM_DEFAULT = {"v0": 30.0, "s0": 2.0, "headway": 1.5, "a_max": 2.0, "b_comf": 3.0, "delta": 4.0,
+               "brake": 8.0, "step": 2.0, "poses": 25}
+
+
+class _OIdm(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("v0", "s0", "headway", "a_max", "b_comf", "delta", "brake", "step")] + \
+        [("poses", C.c_int)]
+
+
+def rollout_idm(obj_off, rg_off, init, accel, curvature, controlled, log_seq, rg, T: int, dt: float,
+                idm=None):
+    """Rollout of T steps in which the uncontrolled objects with a fully
+    valid log window are IDM sim agents (Sec. 3.5).  Returns the dict of
+    rollout() without 'loss', plus 'idm_margin' [T, n] (each agent's
+    decision margin per step, +inf for other objects)."""
+    par = dict(IDM_DEFAULT)
+    par.update(idm or {})
+    off = _i32(obj_off)
+    roff = _i32(rg_off) if rg_off is not None else None
+    S = off.shape[0] - 1
+    n = int(off[-1])
+    st, ls = OState(init), OState(log_seq)
+    g = ORoadgraph(rg) if rg is not None else None
+    traj = OState.empty((T, n))
+    a, k, c = _f64(accel), _f64(curvature), _u8(controlled)
+    out = {"collision": np.zeros((T, n), np.uint8), "overlap_margin": np.zeros((T, n)),
+           "offroad": np.zeros((T, n), np.uint8), "offroad_margin": np.zeros((T, n)),
+           "log_div": np.zeros((T, n)), "idm_margin": np.zeros((T, n))}
+    prm = _OIdm(*[float(par[q]) for q in ("v0", "s0", "headway", "a_max", "b_comf", "delta", "brake", "step")],
+                int(par["poses"]))
+    lib().or_rollout_idm(C.c_int(S), _p(off, C.c_int32), _p(roff, C.c_int32) if roff is not None else None,
+                         C.byref(st.c), _p(a, C.c_double), _p(k, C.c_double), _p(c, C.c_uint8), C.byref(ls.c),
+                         C.byref(g.c) if g is not None else None, C.c_int(T), C.c_double(dt), C.byref(prm),
+                         C.byref(traj.c), _p(out["collision"], C.c_uint8), _p(out["overlap_margin"], C.c_double),
+                         _p(out["offroad"], C.c_uint8) if g is not None else None,
+                         _p(out["offroad_margin"], C.c_double) if g is not None else None,
+                         _p(out["log_div"], C.c_double), _p(out["idm_margin"], C.c_double))
+    out["traj"] = traj.a
+    return out
+
+
 def state_loss(obj_off, state, log, controlled):
     """Loss terms of one state against the log at the same step, per scenario."""
     off = _i32(obj_off)

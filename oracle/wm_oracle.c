@@ -631,6 +631,200 @@ void or_rollout_loss(int S, const int32_t *obj_off, const or_state *init, const 
 }
 
 /* ------------------------------------------------------------------------
+ * IDM sim agents (Sec. 3.5, simulated agent behaviour): uncontrolled objects
+ * follow their logged path with a speed from the intelligent driver model
+ * (Treiber, Hennecke and Helbing, 2000).  The paper gives no parameters or
+ * procedure beyond that, so every step below is a reading:
+ *  - an IDM agent is an uncontrolled object that is valid in every row
+ *    0..T of the log window; every other uncontrolled object replays the
+ *    log.  Its path is the polyline of its logged positions, rows 0..T, with
+ *    cumulative arc length L_0 = 0, L_k = L_{k-1} + |P_k - P_{k-1}|; its
+ *    progress sigma starts at 0 (row 0 is the initial state).
+ *  - pose at progress s: with k the first row having L_k > s, the position
+ *    interpolated linearly between rows k-1 and k at lambda =
+ *    (s - L_{k-1}) / (L_k - L_{k-1}) and the yaw yaw_{k-1} + lambda *
+ *    wrap(yaw_k - yaw_{k-1}); with no such row, row T's position and yaw.
+ *  - lead: lookahead poses at s_m = sigma + m * step, m = 1..M, while
+ *    s_m <= L_T, each carrying the agent's box; the lead is the other valid
+ *    object whose current box overlaps (separating-axis margin > 0) the pose
+ *    with the smallest m, then the lowest index; the gap is (m - 1) * step
+ *    and the lead's speed is its velocity projected on the agent's yaw.
+ *  - acceleration, with v = |(vx, vy)|:
+ *      a = a_max (1 - (v / v0)^delta - (s* / gap)^2),
+ *      s* = s0 + max(0, v T_h + v (v - v_lead) / (2 sqrt(a_max b))),
+ *    without the interaction term when there is no lead, a = -brake when the
+ *    gap is 0, and a clamped to [-brake, a_max].
+ *  - motion: v' = v + a dt and advance v dt + a dt^2 / 2; if v' < 0 the
+ *    agent stops within the step: advance v^2 / (2 |a|), v' = 0.  An agent
+ *    that reaches the end of its path halts there: sigma' = L_T, v' = 0;
+ *    otherwise sigma' = sigma + advance.  The next state is the pose at
+ *    sigma' with velocity v' along its yaw, and length, width and valid of
+ *    log row t.
+ *  - the decision margin of an agent's step is the smallest of the
+ *    |separating-axis margins| of the tests that decide the lead (all objects
+ *    at poses 1..m of the lead, all poses without a lead) and, when the
+ *    halt would change the speed (v' > 0), the distance |L_T - (sigma +
+ *    advance)| that decides the halt at the path end.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double v0, s0, headway, a_max, b_comf, delta, brake, step;
+    int poses;
+} or_idm;
+
+static void idm_pose(long i, int T, long n, const or_state *log, const double *L, double s, double *px,
+                     double *py, double *pyaw)
+{
+    int k = 1;
+    while (k <= T && !(L[k] > s))
+        ++k;
+    if (k > T) {
+        *px = log->x[(long)T * n + i];
+        *py = log->y[(long)T * n + i];
+        *pyaw = log->yaw[(long)T * n + i];
+        return;
+    }
+    long a = (long)(k - 1) * n + i, b = (long)k * n + i;
+    double lam = (s - L[k - 1]) / (L[k] - L[k - 1]);
+    *px = log->x[a] + lam * (log->x[b] - log->x[a]);
+    *py = log->y[a] + lam * (log->y[b] - log->y[a]);
+    *pyaw = log->yaw[a] + lam * wrap_angle(log->yaw[b] - log->yaw[a]);
+}
+
+/* One IDM step of agent i of scenario [o0, o1) from state cur (all objects
+ * at time t-1); writes row t of the next state into nxt and returns the
+ * decision margin. */
+static double idm_step(long i, long o0, long o1, int T, long n, const or_state *cur, const or_state *log_seq,
+                       const double *L, double *sigma, const or_idm *p, double dt, int t, or_state *nxt)
+{
+    double minabs = INFINITY;
+    int lead = -1;
+    double gap = 0.0;
+    for (int m = 1; m <= p->poses && lead < 0; ++m) {
+        double sm = sigma[i] + m * p->step;
+        if (sm > L[T])
+            break;
+        double px, py, pyaw;
+        idm_pose(i, T, n, log_seq, L, sm, &px, &py, &pyaw);
+        for (long j = o0; j < o1; ++j) {
+            if (j == i || !cur->valid[j])
+                continue;
+            double g = or_sat_margin(px, py, pyaw, cur->length[i], cur->width[i], cur->x[j], cur->y[j],
+                                     cur->yaw[j], cur->length[j], cur->width[j]);
+            if (fabs(g) < minabs)
+                minabs = fabs(g);
+            if (g > 0.0 && lead < 0) {
+                lead = (int)j;
+                gap = (m - 1) * p->step;
+            }
+        }
+    }
+    double v = sqrt(cur->vx[i] * cur->vx[i] + cur->vy[i] * cur->vy[i]);
+    double a = p->a_max * (1.0 - pow(v / p->v0, p->delta));
+    if (lead >= 0) {
+        double vl = cur->vx[lead] * cos(cur->yaw[i]) + cur->vy[lead] * sin(cur->yaw[i]);
+        double ss = p->s0 + fmax(0.0, v * p->headway + v * (v - vl) / (2.0 * sqrt(p->a_max * p->b_comf)));
+        a = gap > 0.0 ? a - p->a_max * (ss / gap) * (ss / gap) : -p->brake;
+    }
+    a = fmin(fmax(a, -p->brake), p->a_max);
+    double vn = v + a * dt, adv;
+    if (vn >= 0.0) {
+        adv = v * dt + 0.5 * a * dt * dt;
+    } else {
+        adv = v * v / (2.0 * -a);
+        vn = 0.0;
+    }
+    if (vn > 0.0 && fabs(L[T] - (sigma[i] + adv)) < minabs)
+        minabs = fabs(L[T] - (sigma[i] + adv));
+    if (sigma[i] + adv >= L[T]) {
+        sigma[i] = L[T];
+        vn = 0.0;
+    } else {
+        sigma[i] += adv;
+    }
+    double x, y, yaw;
+    idm_pose(i, T, n, log_seq, L, sigma[i], &x, &y, &yaw);
+    long r = (long)t * n + i;
+    nxt->x[i] = x;
+    nxt->y[i] = y;
+    nxt->yaw[i] = yaw;
+    nxt->vx[i] = vn * cos(yaw);
+    nxt->vy[i] = vn * sin(yaw);
+    nxt->length[i] = log_seq->length[r];
+    nxt->width[i] = log_seq->width[r];
+    nxt->valid[i] = log_seq->valid[r];
+    return minabs;
+}
+
+/* Rollout as or_rollout (no loss) with the uncontrolled objects that have a
+ * fully valid log window driven by IDM.  `margin` [T][n] (optional) receives
+ * each IDM agent's decision margin per step (+inf for other objects). */
+void or_rollout_idm(int S, const int32_t *obj_off, const int32_t *rg_off, const or_state *init,
+                    const double *accel, const double *curvature, const uint8_t *controlled,
+                    const or_state *log_seq, const or_roadgraph *rg, int T, double dt, const or_idm *p,
+                    or_state *traj, uint8_t *collision, double *overlap_margin, uint8_t *offroad,
+                    double *offroad_margin, double *log_div, double *margin)
+{
+    long n = obj_off[S];
+    double *buf = (double *)malloc(sizeof(double) * 14 * n);
+    uint8_t *vbuf = (uint8_t *)malloc(2 * n);
+    double *L = (double *)malloc(sizeof(double) * (size_t)(T + 1) * (size_t)(n > 0 ? n : 1));
+    double *sigma = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    uint8_t *agent = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    or_state a = {buf, buf + n, buf + 2 * n, buf + 3 * n, buf + 4 * n, buf + 5 * n, buf + 6 * n, vbuf};
+    or_state b = {buf + 7 * n, buf + 8 * n, buf + 9 * n, buf + 10 * n, buf + 11 * n, buf + 12 * n,
+                  buf + 13 * n, vbuf + n};
+    for (long i = 0; i < n; ++i) {
+        copy_object(init, (int)i, &a, (int)i);
+        int ok = !controlled[i];
+        for (int k = 0; k <= T && ok; ++k)
+            ok = log_seq->valid[(long)k * n + i] != 0;
+        agent[i] = (uint8_t)ok;
+        double *Li = L + (size_t)i * (T + 1);
+        Li[0] = 0.0;
+        for (int k = 1; k <= T; ++k) {
+            long r0 = (long)(k - 1) * n + i, r1 = (long)k * n + i;
+            Li[k] = Li[k - 1] + sqrt((log_seq->x[r1] - log_seq->x[r0]) * (log_seq->x[r1] - log_seq->x[r0]) +
+                                     (log_seq->y[r1] - log_seq->y[r0]) * (log_seq->y[r1] - log_seq->y[r0]));
+        }
+    }
+    or_state *cur = &a, *nxt = &b;
+    for (int t = 1; t <= T; ++t) {
+        or_state lg = state_row(log_seq, t, n);
+        long row = (long)(t - 1) * n;
+        or_bicycle_forward((int)n, cur, accel + (t - 1) * n, curvature + (t - 1) * n, controlled, &lg, dt, nxt);
+        for (int s = 0; s < S; ++s)
+            for (long i = obj_off[s]; i < obj_off[s + 1]; ++i) {
+                double mg = INFINITY;
+                if (agent[i])
+                    mg = idm_step(i, obj_off[s], obj_off[s + 1], T, n, cur, log_seq, L + (size_t)i * (T + 1),
+                                  sigma, p, dt, t, nxt);
+                if (margin)
+                    margin[row + i] = mg;
+            }
+        if (traj) {
+            or_state tr = state_row(traj, t - 1, n);
+            for (long i = 0; i < n; ++i)
+                copy_object(nxt, (int)i, &tr, (int)i);
+        }
+        or_overlap(S, obj_off, nxt, NULL, collision ? collision + row : NULL,
+                   overlap_margin ? overlap_margin + row : NULL);
+        if (rg && (offroad || offroad_margin))
+            or_offroad(S, obj_off, rg_off, nxt, rg, 0.0, offroad_margin ? offroad_margin + row : NULL,
+                       offroad ? offroad + row : NULL, NULL, NULL, NULL, NULL);
+        if (log_div)
+            or_log_divergence((int)n, nxt, &lg, log_div + row);
+        or_state *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    free(buf);
+    free(vbuf);
+    free(L);
+    free(sigma);
+    free(agent);
+}
+
+/* ------------------------------------------------------------------------
  * Reverse-mode gradient of the rollout loss with respect to the actions,
  * by hand, with the whole forward trajectory kept (no checkpointing).
  * Conventions at non-smooth points: sgn(0) = +1 for |.|; the lowest axis

@@ -457,9 +457,10 @@ static int rollout_checks(const wm_batch *batch, const wm_state *init, const wm_
     return check_dt(dt);
 }
 
-int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act_seq, const wm_state *log_seq,
-               const wm_roadgraph *rg, int32_t T, float dt, int32_t ckpt_every, wm_state *ckpt, wm_state *traj,
-               wm_metrics *met_seq, float *loss, const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)
+static int rollout_impl(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
+                        const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, int32_t ckpt_every,
+                        wm_state *ckpt, wm_state *traj, wm_metrics *met_seq, float *loss, const wm_idm *idm,
+                        const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)
 {
     CHECK(rollout_checks(batch, init, act_seq, log_seq, T, dt, ckpt_every));
     if (rg)
@@ -513,6 +514,14 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
     a.uoff = (const int32_t *)(w + L.uoff);
     a.units = (const int2 *)(w + L.units);
     a.counter = (int32_t *)(w + L.counter);
+    if (idm) {
+        a.has_idm = 1;
+        a.idm = *idm;
+        a.idmL = (const float *)(w + L.idmL);
+        a.idmA = (const uint8_t *)(w + L.idmA);
+        wm::launch_idm_paths(batch->total_objects, T, *log_seq, act_seq->controlled, (float *)(w + L.idmL),
+                             (uint8_t *)(w + L.idmA), s);
+    }
     const int U = 64 * tn.CW;
     const int bound = batch->total_objects / U + batch->num_scenarios;
     const int grid = wm::rollout_grid(tn.G, tn.CW, batch->max_objects, bound);
@@ -522,7 +531,36 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
     }
     if (loss)
         wm::launch_loss_reduce(batch->num_scenarios, a.uoff, a.lossp, loss, s);
-    return device_status("wm_rollout");
+    return device_status(idm ? "wm_rollout_idm" : "wm_rollout");
+}
+
+int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act_seq, const wm_state *log_seq,
+               const wm_roadgraph *rg, int32_t T, float dt, int32_t ckpt_every, wm_state *ckpt, wm_state *traj,
+               wm_metrics *met_seq, float *loss, const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)
+{
+    return rollout_impl(batch, init, act_seq, log_seq, rg, T, dt, ckpt_every, ckpt, traj, met_seq, loss, nullptr,
+                        tune, ws, ws_bytes, stream);
+}
+
+int wm_rollout_idm(const wm_batch *batch, const wm_state *init, const wm_action *act_seq, const wm_state *log_seq,
+                   const wm_roadgraph *rg, int32_t T, float dt, const wm_idm *idm, wm_state *traj,
+                   wm_metrics *met_seq, const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!idm)
+        return fail(WM_ERR_NULL, "idm parameters are NULL");
+    const float pos[] = {idm->desired_speed, idm->max_accel, idm->comfort_decel, idm->exponent, idm->max_brake,
+                         idm->lookahead_step};
+    for (float v : pos)
+        if (!(v > 0.f) || !std::isfinite(v))
+            return fail(WM_ERR_RANGE, "idm: speeds, accelerations, exponent and step must be finite and > 0");
+    if (!(idm->min_gap >= 0.f) || !(idm->time_headway >= 0.f) || !std::isfinite(idm->min_gap) ||
+        !std::isfinite(idm->time_headway))
+        return fail(WM_ERR_RANGE, "idm: min_gap and time_headway must be finite and >= 0");
+    if (idm->lookahead_poses < 1 || idm->lookahead_poses > WM_MAX_IDM_POSES)
+        return fail(WM_ERR_RANGE, "idm: lookahead_poses = %d not in [1, %d]", idm->lookahead_poses,
+                    WM_MAX_IDM_POSES);
+    return rollout_impl(batch, init, act_seq, log_seq, rg, T, dt, 0, nullptr, traj, met_seq, nullptr, idm, tune, ws,
+                        ws_bytes, stream);
 }
 
 int wm_rollout_backward(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,

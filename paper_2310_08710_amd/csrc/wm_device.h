@@ -113,6 +113,55 @@ __device__ __forceinline__ float sat_margin(const Box &a, const Box &b)
     return fminf(fminf(g1, g2), fminf(g3, g4));
 }
 
+// ---------------------------------------------------------------------------
+// IDM sim agents (Sec. 3.5; intelligent driver model).  An agent's path is
+// its logged positions, rows 0..T of the log window, with cumulative arc
+// lengths L (time-major [T+1][n] like the logs).
+// ---------------------------------------------------------------------------
+
+// Pose at arc length s on the path of object g: linear between the rows k-1
+// and k around the first k with L_k > s (yaw along the shorter arc between the
+// logged yaws), or row T's pose when there is no such row.
+__device__ __forceinline__ void idm_pose(const wm_state &log, const float *__restrict__ L, long n, int T, long g,
+                                         float s, float &x, float &y, float &yaw)
+{
+    int lo = 1, hi = T + 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (L[(long)mid * n + g] > s)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    if (lo > T) {
+        const long r = (long)T * n + g;
+        x = log.x[r];
+        y = log.y[r];
+        yaw = log.yaw[r];
+        return;
+    }
+    const long a = (long)(lo - 1) * n + g, b = (long)lo * n + g;
+    const float La = L[a];
+    const float lam = (s - La) / (L[b] - La);
+    x = __builtin_fmaf(lam, log.x[b] - log.x[a], log.x[a]);
+    y = __builtin_fmaf(lam, log.y[b] - log.y[a], log.y[a]);
+    yaw = __builtin_fmaf(lam, wrap_angle(log.yaw[b] - log.yaw[a]), log.yaw[a]);
+}
+
+// IDM acceleration for speed v; `lead` selects the interaction term with gap
+// `gap` and lead speed vl (along the agent's yaw).
+__device__ __forceinline__ float idm_accel(const wm_idm &p, float v, bool lead, float gap, float vl)
+{
+    float a = p.max_accel * (1.0f - powf(v / p.desired_speed, p.exponent));
+    if (lead) {
+        const float ss =
+            p.min_gap + fmaxf(0.0f, v * p.time_headway + v * (v - vl) / (2.0f * sqrtf(p.max_accel * p.comfort_decel)));
+        const float q = ss / gap;
+        a = gap > 0.0f ? a - p.max_accel * (q * q) : -p.max_brake;
+    }
+    return fminf(fmaxf(a, -p.max_brake), p.max_accel);
+}
+
 // Gradient of sat_margin with respect to (x, y, yaw) of a and of b, through
 // the arg-min axis (lowest axis index on ties), sgn(0) = +1.
 __device__ __forceinline__ void sat_margin_grad(const Box &a, const Box &b, float ga[3], float gb[3])

@@ -622,6 +622,122 @@ __global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
 // all N_s objects (needed by the slice's pairs), then for the slice objects
 // the overlap, off-road, log divergence, loss terms, outputs and checkpoints.
 // ---------------------------------------------------------------------------
+// IDM sim agents, per step from the states at t-1 in LDS: the lead of every
+// agent (the first lookahead pose, then the lowest object index, whose box
+// overlaps another valid object's current box) by an LDS atomic minimum over
+// (agent, pose) work items, then each agent's acceleration into ia[].
+// Contains three block barriers.
+__device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, int o0, int N, const float *sig, float *ia,
+                                       int *lk, const uint8_t *agent)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const long n = A.n;
+    const int M = A.idm.lookahead_poses;
+    for (int i = tid; i < N; i += nthr)
+        lk[i] = 0x7fffffff;
+    __syncthreads();
+    for (int it = tid; it < N * M; it += nthr) {
+        const int i = it / M, m = it - i * M + 1;
+        if (!agent[i])
+            continue;
+        const long g = o0 + i;
+        const float sm = __builtin_fmaf((float)m, A.idm.lookahead_step, sig[i]);
+        if (sm > A.idmL[(long)A.T * n + g])
+            continue;
+        float px, py, pyaw, ps, pc;
+        idm_pose(A.log, A.idmL, n, A.T, g, sm, px, py, pyaw);
+        sincosf(pyaw, &ps, &pc);
+        const Box a{px, py, pc, ps, 0.5f * L.len[i], 0.5f * L.wid[i]};
+        const float ra = 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i]));
+        for (int j = 0; j < N; ++j) {
+            if (j == i || !L.valid[j])
+                continue;
+            // boxes lie within their circumscribed circles
+            const float dx = L.x[j] - px, dy = L.y[j] - py;
+            const float rr = ra + 0.5f * sqrtf(__builtin_fmaf(L.wid[j], L.wid[j], L.len[j] * L.len[j])) + 1e-3f;
+            if (__builtin_fmaf(dy, dy, dx * dx) > rr * rr)
+                continue;
+            const Box b{L.x[j], L.y[j], L.c[j], L.s[j], 0.5f * L.len[j], 0.5f * L.wid[j]};
+            if (sat_margin(a, b) > 0.f) {
+                atomicMin(&lk[i], m * 2048 + j);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += nthr) {
+        if (!agent[i])
+            continue;
+        const int key = lk[i];
+        const float v = sqrtf(__builtin_fmaf(L.vy[i], L.vy[i], L.vx[i] * L.vx[i]));
+        if (key == 0x7fffffff) {
+            ia[i] = idm_accel(A.idm, v, false, 0.f, 0.f);
+        } else {
+            const int m = key >> 11, j = key & 2047;
+            const float vl = __builtin_fmaf(L.vy[j], L.s[i], L.vx[j] * L.c[i]);
+            ia[i] = idm_accel(A.idm, v, true, (float)(m - 1) * A.idm.lookahead_step, vl);
+        }
+    }
+    __syncthreads();
+}
+
+// Advance IDM agent i (global g) with acceleration a along its path; the
+// next state's length, width and valid come from log row `row`.
+__device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int i, long g, long row, float *sig,
+                                         float a)
+{
+    const float dt = A.dt;
+    const float v = sqrtf(__builtin_fmaf(L.vy[i], L.vy[i], L.vx[i] * L.vx[i]));
+    float vn = __builtin_fmaf(a, dt, v), adv;
+    if (vn >= 0.f) {
+        adv = __builtin_fmaf(v, dt, 0.5f * a * dt * dt);
+    } else {
+        adv = v * v / (2.0f * -a);
+        vn = 0.f;
+    }
+    const float Lend = A.idmL[(long)A.T * A.n + g];
+    if (sig[i] + adv >= Lend) {   // the end of the path: halt there
+        sig[i] = Lend;
+        vn = 0.f;
+    } else {
+        sig[i] += adv;
+    }
+    float x, y, yaw, sn, cs;
+    idm_pose(A.log, A.idmL, A.n, A.T, g, sig[i], x, y, yaw);
+    sincosf(yaw, &sn, &cs);
+    L.x[i] = x;
+    L.y[i] = y;
+    L.yaw[i] = yaw;
+    L.vx[i] = vn * cs;
+    L.vy[i] = vn * sn;
+    L.c[i] = cs;
+    L.s[i] = sn;
+    L.len[i] = A.log.length[row + g];
+    L.wid[i] = A.log.width[row + g];
+    L.valid[i] = A.log.valid[row + g];
+}
+
+// Arc lengths of every object's logged path, rows 0..T (time-major), and the
+// IDM agent flag: uncontrolled and valid in every row.
+__global__ __launch_bounds__(256) void k_idm_paths(int n, int T, wm_state log, const uint8_t *__restrict__ controlled,
+                                                   float *__restrict__ Lout, uint8_t *__restrict__ agent)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n)
+        return;
+    bool ok = !controlled[g] && log.valid[g];
+    float acc = 0.f;
+    Lout[g] = 0.f;
+    for (int k = 1; k <= T; ++k) {
+        const long a = (long)(k - 1) * n + g, b = (long)k * n + g;
+        const float dx = log.x[b] - log.x[a], dy = log.y[b] - log.y[a];
+        acc = acc + sqrtf(__builtin_fmaf(dy, dy, dx * dx));
+        Lout[b] = acc;
+        ok = ok && log.valid[b];
+    }
+    agent[g] = (uint8_t)ok;
+}
+
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_rollout(RollArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -636,6 +752,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     int *nidx = (int *)(sk + SL);
     float *red = (float *)(nidx + SL);
     float *wsum = red + nthr;
+    float *sig = wsum + 16;              // IDM: path progress
+    float *ia = sig + A.maxN;            // IDM: acceleration of the step
+    int *lk = (int *)(ia + A.maxN);      // IDM: lead key m * 2048 + j
+    uint8_t *agent = (uint8_t *)(lk + A.maxN);
     __shared__ int s_unit;
     const int tid = threadIdx.x;
     const long n = A.n;
@@ -659,6 +779,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int i = tid; i < N; i += nthr) {
             load_object(L, i, A.init, o0 + i);
             L.ctrl[i] = A.act.controlled[o0 + i];
+            if (A.has_idm) {
+                sig[i] = 0.f;
+                agent[i] = A.idmA[o0 + i];
+            }
         }
         if (A.has_ckpt)
             for (int il = tid; il < Ns; il += nthr)
@@ -667,11 +791,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         float my_loss = 0.f;
         for (int t = 1; t <= A.T; ++t) {
             const long row = (long)t * n, arow = (long)(t - 1) * n;
+            if (A.has_idm)
+                idm_leads(A, L, o0, N, sig, ia, lk, agent);
             for (int i = tid; i < N; i += nthr) {
                 const long g = o0 + i;
                 const float pvx = L.vx[i], pvy = L.vy[i], pyaw = L.yaw[i];
                 const bool pvalid = L.valid[i];
-                if (!L.ctrl[i]) {
+                if (!L.ctrl[i] && A.has_idm && agent[i]) {
+                    idm_move(A, L, i, g, row, sig, ia[i]);
+                } else if (!L.ctrl[i]) {
                     load_object(L, i, A.log, row + g);
                 } else if (L.valid[i]) {
                     float x = L.x[i], y = L.y[i], yaw = L.yaw[i], vx = L.vx[i], vy = L.vy[i];
@@ -825,7 +953,13 @@ void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
 size_t rollout_lds_bytes(int maxN, int G, int CW)
 {
     const int nthr = 64 * CW * G;
-    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4;
+    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up((size_t)maxN * 13, 16);
+}
+
+void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float *L, uint8_t *agent,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_idm_paths, dim3((n + 255) / 256), dim3(256), 0, st, n, T, log, controlled, L, agent);
 }
 
 int rollout_grid(int G, int CW, int maxN, int n_units_bound)

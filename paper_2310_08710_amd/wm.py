@@ -58,6 +58,18 @@ class CTuning(C.Structure):
     _fields_ = [("unit_objects", C.c_int32), ("edge_splits", C.c_int32)]
 
 
+class CIdm(C.Structure):
+    _fields_ = [(k, C.c_float) for k in ("desired_speed", "min_gap", "time_headway", "max_accel", "comfort_decel",
+                                         "exponent", "max_brake", "lookahead_step")] + [("lookahead_poses", C.c_int32)]
+
+
+# IDM sim-agent parameters used when none are given (Sec. 3.5 gives none;
+# a urban-speed reading): v0 30 m/s, s0 2 m, headway 1.5 s, a_max 2 m/s^2,
+# b 3 m/s^2, delta 4, hardest braking 8 m/s^2, 25 lookahead poses 2 m apart.
+IDM_DEFAULT = {"desired_speed": 30.0, "min_gap": 2.0, "time_headway": 1.5, "max_accel": 2.0, "comfort_decel": 3.0,
+               "exponent": 4.0, "max_brake": 8.0, "lookahead_step": 2.0, "lookahead_poses": 25}
+
+
 class WMError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("wm error %d (%s): %s" % (code, error_string(code), msg))
@@ -92,6 +104,9 @@ def lib() -> C.CDLL:
         L.wm_rollout.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
                                  C.POINTER(CRoadgraph), C.c_int32, C.c_float, C.c_int32, C.POINTER(CState),
                                  C.POINTER(CState), C.POINTER(CMetrics), _P, C.POINTER(CTuning), _P, C.c_size_t, _P]
+        L.wm_rollout_idm.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
+                                     C.POINTER(CRoadgraph), C.c_int32, C.c_float, C.POINTER(CIdm),
+                                     C.POINTER(CState), C.POINTER(CMetrics), C.POINTER(CTuning), _P, C.c_size_t, _P]
         L.wm_rollout_backward.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction),
                                           C.POINTER(CState), C.c_int32, C.c_float, C.c_int32, C.POINTER(CState),
                                           _P, _P, _P, _P, C.c_size_t, _P]
@@ -334,6 +349,25 @@ def rollout(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: Opti
                             T, dt, ckpt_every, C.byref(ck) if ck is not None else None,
                             C.byref(tr) if tr is not None else None, C.byref(m) if m is not None else None,
                             _ptr(loss), _tune(tune), ws.data_ptr(), ws.numel(), _stream(stream)))
+
+
+def rollout_idm(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: Optional[Roadgraph], T: int,
+                dt: float, ws: torch.Tensor, idm: Optional[dict] = None, traj: Optional[State] = None,
+                metrics: Optional[Metrics] = None, tune=None, stream=None):
+    """Fused rollout with IDM sim agents (every uncontrolled object with a
+    fully valid log window); idm overrides entries of IDM_DEFAULT."""
+    par = dict(IDM_DEFAULT)
+    par.update(idm or {})
+    p = CIdm(*[float(par[k]) for k in ("desired_speed", "min_gap", "time_headway", "max_accel", "comfort_decel",
+                                       "exponent", "max_brake", "lookahead_step")], int(par["lookahead_poses"]))
+    b, i, a, l = batch.c(), init.c(), act_seq.c(), log_seq.c()
+    r = rg.c() if rg is not None else None
+    tr = traj.c() if traj is not None else None
+    m = metrics.c() if metrics is not None else None
+    _check(lib().wm_rollout_idm(C.byref(b), C.byref(i), C.byref(a), C.byref(l), C.byref(r) if r is not None else None,
+                                T, dt, C.byref(p), C.byref(tr) if tr is not None else None,
+                                C.byref(m) if m is not None else None, _tune(tune), ws.data_ptr(), ws.numel(),
+                                _stream(stream)))
 
 
 def rollout_backward(batch: Batch, init: State, act_seq: Action, log_seq: State, T: int, dt: float, ckpt_every: int,

@@ -165,3 +165,26 @@ def test_inverse_and_overlap_validation():
     assert L.wm_overlap(C.byref(b), C.byref(s), None, FAKE, None, None, None, None) == wm.WM_ERR_NULL
     # nothing requested: a no-op that never launches
     assert L.wm_overlap(C.byref(b), C.byref(s), None, None, None, None, None, None) == wm.WM_OK
+
+
+def _idm(**kw):
+    p = dict(wm.IDM_DEFAULT)
+    p.update(kw)
+    return wm.CIdm(*[float(p[k]) for k in ("desired_speed", "min_gap", "time_headway", "max_accel",
+                                           "comfort_decel", "exponent", "max_brake", "lookahead_step")],
+                   int(p["lookahead_poses"]))
+
+
+@pytest.mark.parametrize("bad", [{"desired_speed": 0.0}, {"max_brake": -1.0}, {"lookahead_step": float("nan")},
+                                 {"lookahead_poses": 0}, {"lookahead_poses": 65}, {"min_gap": -0.5},
+                                 {"time_headway": float("inf")}])
+def test_idm_rollout_rejects_bad_parameters(bad):
+    b = _batch()
+    p = _idm(**bad)
+    rc = wm.lib().wm_rollout_idm(C.byref(b), C.byref(_state()), C.byref(_act()), C.byref(_state()), None, 10, 0.1,
+                                 C.byref(p), None, None, None, FAKE, 1 << 30, None)
+    assert rc == 2, _msg()     # WM_ERR_RANGE
+    assert "idm" in _msg()
+    rc = wm.lib().wm_rollout_idm(C.byref(b), C.byref(_state()), C.byref(_act()), C.byref(_state()), None, 10, 0.1,
+                                 None, None, None, None, FAKE, 1 << 30, None)
+    assert rc == 1             # WM_ERR_NULL
