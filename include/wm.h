@@ -236,7 +236,9 @@ int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
  *   init       state at the current time (row 0 of the logs)
  *   act_seq    actions [T][n]; controlled [n]
  *   log_seq    logged states [T+1][n], row 0 = the initial time
- *   rg         road graph (off-road metrics); may be NULL (no off-road)
+ *   rg         road graph (off-road metrics); may be NULL (no off-road); the
+ *              off-road scan runs only if met_seq requests offroad,
+ *              offroad_margin or reward
  *   ckpt       [ceil(T/ckpt_every)][n] states at t = 0, c, 2c, ... or NULL
  *   traj       [T][n] successor states or NULL
  *   met_seq    [T][n] metrics or NULL (members may be NULL)

@@ -460,7 +460,7 @@ static int rollout_checks(const wm_batch *batch, const wm_state *init, const wm_
 static int rollout_impl(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
                         const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, int32_t ckpt_every,
                         wm_state *ckpt, wm_state *traj, wm_metrics *met_seq, float *loss, const wm_idm *idm,
-                        const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)
+                        const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream, bool force_off = false)
 {
     CHECK(rollout_checks(batch, init, act_seq, log_seq, T, dt, ckpt_every));
     if (rg)
@@ -482,9 +482,13 @@ static int rollout_impl(const wm_batch *batch, const wm_state *init, const wm_ac
         return fail(WM_ERR_UNSUPPORTED, "rollout needs %zu bytes of LDS", lds);
     hipStream_t s = (hipStream_t)stream;
     unsigned char *w = (unsigned char *)ws;
-    if (rg)
+    // the off-road scan runs only when an output needs it
+    // (force_off: the autotuner times the scan without outputs)
+    const bool want_off =
+        rg && (force_off || (met_seq && (met_seq->offroad || met_seq->offroad_margin || met_seq->reward)));
+    if (want_off)
         wm::launch_compact_edges(*batch, *rg, w, L, s);
-    wm::launch_build_units(*batch, 64 * tn.CW, rg ? (const int32_t *)(w + L.ecount) : nullptr, w, L, s);
+    wm::launch_build_units(*batch, 64 * tn.CW, want_off ? (const int32_t *)(w + L.ecount) : nullptr, w, L, s);
     wm::RollArgs a{};
     a.S = batch->num_scenarios;
     a.n = batch->total_objects;
@@ -499,7 +503,7 @@ static int rollout_impl(const wm_batch *batch, const wm_state *init, const wm_ac
     a.init = *init;
     a.act = *act_seq;
     a.log = *log_seq;
-    a.has_rg = rg != nullptr;
+    a.has_rg = want_off;
     a.has_ckpt = ckpt != nullptr;
     a.has_traj = traj != nullptr;
     a.want_loss = loss != nullptr;
@@ -618,14 +622,14 @@ int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *ac
         wm_tuning t{c[0], c[1]};
         if (wm::rollout_lds_bytes(batch->max_objects, t.edge_splits, t.unit_objects / 64) > 160 * 1024)
             continue;
-        int rc = wm_rollout(batch, init, act_seq, log_seq, rg, T, dt, 0, nullptr, nullptr, nullptr, nullptr, &t, ws,
-                            ws_bytes, stream);
+        int rc = rollout_impl(batch, init, act_seq, log_seq, rg, T, dt, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              &t, ws, ws_bytes, stream, true);
         if (rc != WM_OK)
             break;
         hipEventRecord(e0, s);
         for (int r = 0; r < 2; ++r)
-            wm_rollout(batch, init, act_seq, log_seq, rg, T, dt, 0, nullptr, nullptr, nullptr, nullptr, &t, ws,
-                       ws_bytes, stream);
+            (void)rollout_impl(batch, init, act_seq, log_seq, rg, T, dt, 0, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, &t, ws, ws_bytes, stream, true);
         hipEventRecord(e1, s);
         hipEventSynchronize(e1);
         float ms = 0.f;

@@ -622,20 +622,52 @@ __global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
 // all N_s objects (needed by the slice's pairs), then for the slice objects
 // the overlap, off-road, log divergence, loss terms, outputs and checkpoints.
 // ---------------------------------------------------------------------------
+// Largest scenario for which the IDM lead search keeps a per-agent bit mask
+// of candidate objects in LDS (maxN^2 / 8 bytes); larger ones test every
+// object.
+constexpr int kIdmMaskMaxN = 256;
+
 // IDM sim agents, per step from the states at t-1 in LDS: the lead of every
 // agent (the first lookahead pose, then the lowest object index, whose box
 // overlaps another valid object's current box) by an LDS atomic minimum over
-// (agent, pose) work items, then each agent's acceleration into ia[].
-// Contains three block barriers.
+// (agent, pose) work items, then each agent's acceleration into ia[].  All
+// poses of agent i lie within M * step (arc length) of its pose at sig[i], so
+// only objects within M * step + r_i + r_j of that point (r: half diagonal)
+// can overlap one of them; with maxN <= kIdmMaskMaxN those candidates are
+// collected first as a bit mask per agent.  Contains four block barriers.
 __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, int o0, int N, const float *sig, float *ia,
-                                       int *lk, const uint8_t *agent)
+                                          int *lk, const uint8_t *agent, float *pc, uint32_t *mask)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const long n = A.n;
     const int M = A.idm.lookahead_poses;
-    for (int i = tid; i < N; i += nthr)
+    const bool use_mask = A.maxN <= kIdmMaskMaxN;
+    const int W = (N + 31) >> 5;
+    for (int i = tid; i < N; i += nthr) {
         lk[i] = 0x7fffffff;
+        if (use_mask && agent[i]) {
+            float yaw;
+            idm_pose(A.log, A.idmL, n, A.T, o0 + i, sig[i], pc[2 * i], pc[2 * i + 1], yaw);
+        }
+    }
+    if (use_mask)
+        for (int k = tid; k < N * W; k += nthr)
+            mask[k] = 0u;
     __syncthreads();
+    const float reach = (float)M * A.idm.lookahead_step;
+    if (use_mask) {
+        for (int it = tid; it < N * N; it += nthr) {
+            const int i = it / N, j = it - i * N;
+            if (!agent[i] || j == i || !L.valid[j])
+                continue;
+            const float dx = L.x[j] - pc[2 * i], dy = L.y[j] - pc[2 * i + 1];
+            const float rr = reach + 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i])) +
+                             0.5f * sqrtf(__builtin_fmaf(L.wid[j], L.wid[j], L.len[j] * L.len[j])) + 1e-2f;
+            if (__builtin_fmaf(dy, dy, dx * dx) <= rr * rr)
+                atomicOr(&mask[i * W + (j >> 5)], 1u << (j & 31));
+        }
+        __syncthreads();
+    }
     for (int it = tid; it < N * M; it += nthr) {
         const int i = it / M, m = it - i * M + 1;
         if (!agent[i])
@@ -644,24 +676,35 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
         const float sm = __builtin_fmaf((float)m, A.idm.lookahead_step, sig[i]);
         if (sm > A.idmL[(long)A.T * n + g])
             continue;
-        float px, py, pyaw, ps, pc;
+        float px, py, pyaw, ps, pcs;
         idm_pose(A.log, A.idmL, n, A.T, g, sm, px, py, pyaw);
-        sincosf(pyaw, &ps, &pc);
-        const Box a{px, py, pc, ps, 0.5f * L.len[i], 0.5f * L.wid[i]};
+        sincosf(pyaw, &ps, &pcs);
+        const Box a{px, py, pcs, ps, 0.5f * L.len[i], 0.5f * L.wid[i]};
         const float ra = 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i]));
-        for (int j = 0; j < N; ++j) {
-            if (j == i || !L.valid[j])
-                continue;
-            // boxes lie within their circumscribed circles
-            const float dx = L.x[j] - px, dy = L.y[j] - py;
-            const float rr = ra + 0.5f * sqrtf(__builtin_fmaf(L.wid[j], L.wid[j], L.len[j] * L.len[j])) + 1e-3f;
-            if (__builtin_fmaf(dy, dy, dx * dx) > rr * rr)
-                continue;
-            const Box b{L.x[j], L.y[j], L.c[j], L.s[j], 0.5f * L.len[j], 0.5f * L.wid[j]};
-            if (sat_margin(a, b) > 0.f) {
-                atomicMin(&lk[i], m * 2048 + j);
-                break;
+        // objects in ascending index order; the first overlap is this pose's
+        // lowest index
+        for (int w = 0; w < W; ++w) {
+            uint32_t bits = use_mask ? mask[i * W + w] : 0xffffffffu;
+            bool hit = false;
+            while (bits) {
+                const int j = 32 * w + __builtin_ctz(bits);
+                bits &= bits - 1u;
+                if (j >= N || j == i || !L.valid[j])
+                    continue;
+                // boxes lie within their circumscribed circles
+                const float dx = L.x[j] - px, dy = L.y[j] - py;
+                const float rr = ra + 0.5f * sqrtf(__builtin_fmaf(L.wid[j], L.wid[j], L.len[j] * L.len[j])) + 1e-3f;
+                if (__builtin_fmaf(dy, dy, dx * dx) > rr * rr)
+                    continue;
+                const Box b{L.x[j], L.y[j], L.c[j], L.s[j], 0.5f * L.len[j], 0.5f * L.wid[j]};
+                if (sat_margin(a, b) > 0.f) {
+                    atomicMin(&lk[i], m * 2048 + j);
+                    hit = true;
+                    break;
+                }
             }
+            if (hit)
+                break;
         }
     }
     __syncthreads();
@@ -756,6 +799,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     float *ia = sig + A.maxN;            // IDM: acceleration of the step
     int *lk = (int *)(ia + A.maxN);      // IDM: lead key m * 2048 + j
     uint8_t *agent = (uint8_t *)(lk + A.maxN);
+    float *pc = (float *)(agent + align_up((size_t)A.maxN, 16));   // IDM: pose at sig (x, y)
+    uint32_t *mask = (uint32_t *)(pc + 2 * A.maxN);                   // IDM: candidate bit masks
     __shared__ int s_unit;
     const int tid = threadIdx.x;
     const long n = A.n;
@@ -792,7 +837,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int t = 1; t <= A.T; ++t) {
             const long row = (long)t * n, arow = (long)(t - 1) * n;
             if (A.has_idm)
-                idm_leads(A, L, o0, N, sig, ia, lk, agent);
+                idm_leads(A, L, o0, N, sig, ia, lk, agent, pc, mask);
             for (int i = tid; i < N; i += nthr) {
                 const long g = o0 + i;
                 const float pvx = L.vx[i], pvy = L.vy[i], pyaw = L.yaw[i];
@@ -953,7 +998,9 @@ void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
 size_t rollout_lds_bytes(int maxN, int G, int CW)
 {
     const int nthr = 64 * CW * G;
-    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up((size_t)maxN * 13, 16);
+    const size_t idm = (size_t)maxN * 12 + align_up((size_t)maxN, 16) + (size_t)maxN * 8 +
+                       (maxN <= kIdmMaskMaxN ? (size_t)maxN * ((maxN + 31) / 32) * 4 : 0);
+    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up(idm, 16);
 }
 
 void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float *L, uint8_t *agent,

@@ -406,12 +406,15 @@ def profile_collect(which: int):
 
 
 class RolloutLoss(torch.autograd.Function):
-    """Differentiable rollout: forward = wm_rollout (loss + checkpoints),
-    backward = wm_rollout_backward (hand-written adjoint).  Inputs accel /
-    curvature [T, n] float32; returns the per-scenario loss [S]."""
+    """Differentiable rollout: forward = wm_rollout (loss + checkpoints, and
+    the step metrics into `metrics` unless it is None), backward =
+    wm_rollout_backward (hand-written adjoint).  Inputs accel / curvature
+    [T, n] float32; returns the per-scenario loss [S].  Call as
+    apply(accel, curvature, batch, init, controlled, log_seq, rg, T, dt,
+    ckpt_every, metrics)."""
 
     @staticmethod
-    def forward(ctx, accel, curvature, batch, init, controlled, log_seq, rg, T, dt, ckpt_every):
+    def forward(ctx, accel, curvature, batch, init, controlled, log_seq, rg, T, dt, ckpt_every, metrics):
         dev = accel.device
         accel = accel.detach().contiguous()
         curvature = curvature.detach().contiguous()
@@ -420,7 +423,7 @@ class RolloutLoss(torch.autograd.Function):
         ckpt = State.empty((n_ck, batch.total_objects), dev)
         ws = batch.workspace(T, ckpt_every)
         loss = torch.empty(batch.num_scenarios, dtype=torch.float32, device=dev)
-        rollout(batch, init, act, log_seq, rg, T, dt, ws, ckpt_every=ckpt_every, ckpt=ckpt, loss=loss)
+        rollout(batch, init, act, log_seq, rg, T, dt, ws, ckpt_every=ckpt_every, ckpt=ckpt, metrics=metrics, loss=loss)
         ctx.saved = (batch, init, act, log_seq, T, dt, ckpt_every, ckpt, ws)
         return loss
 
@@ -430,7 +433,7 @@ class RolloutLoss(torch.autograd.Function):
         ga = torch.empty_like(act.accel)
         gk = torch.empty_like(act.curvature)
         rollout_backward(batch, init, act, log_seq, T, dt, ckpt_every, ckpt, dloss.contiguous().float(), ga, gk, ws)
-        return ga, gk, None, None, None, None, None, None, None, None
+        return ga, gk, None, None, None, None, None, None, None, None, None
 
 
 # ---------------------------------------------------------------------------

@@ -136,7 +136,7 @@ def test_config3_adjoint_full_size():
     T = sc.steps
     a = ds.act_seq.accel.clone().requires_grad_(True)
     k = ds.act_seq.curvature.clone().requires_grad_(True)
-    L = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, ds.rg, T, sc.dt, 10)
+    L = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, ds.rg, T, sc.dt, 10, None)
     L.sum().backward()
     torch.cuda.synchronize()
     obj_off, _, lw, _, oa, ok_, ctrl, cols = _sub(sc, [0, 1, 2, 3])
@@ -202,7 +202,7 @@ def test_config4_adjoint_full_size(config4):
     T = sc.steps
     a = ds.act_seq.accel.clone().requires_grad_(True)
     k = ds.act_seq.curvature.clone().requires_grad_(True)
-    L = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, ds.rg, T, sc.dt, 10)
+    L = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, ds.rg, T, sc.dt, 10, None)
     L.sum().backward()
     torch.cuda.synchronize()
     for s in (1, 3000):

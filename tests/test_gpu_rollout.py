@@ -161,7 +161,7 @@ def test_adjoint_matches_oracle_gradient():
     a = ds.act_seq.accel.clone().requires_grad_(True)
     k = ds.act_seq.curvature.clone().requires_grad_(True)
     dl = torch.tensor([1.0, 0.5, 2.0, 1.5], device=dev)
-    loss = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, None, T, sc.dt, 5)
+    loss = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, None, T, sc.dt, 5, None)
     (loss * dl).sum().backward()
     torch.cuda.synchronize()
     lw = sc.log_window()
@@ -189,7 +189,7 @@ def test_adjoint_checkpoint_interval_invariance():
     for K in (1, 5, 17):
         a = ds.act_seq.accel.clone().requires_grad_(True)
         k = ds.act_seq.curvature.clone().requires_grad_(True)
-        loss = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, None, T, sc.dt, K)
+        loss = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, None, T, sc.dt, K, None)
         loss.sum().backward()
         grads.append((a.grad.clone(), k.grad.clone(), loss.detach().clone()))
     for g in grads[1:]:

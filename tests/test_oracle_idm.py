@@ -85,7 +85,10 @@ def test_follows_a_curved_logged_path():
             u = np.clip(np.dot([px[t], py[t]] - a, b - a) / np.dot(b - a, b - a), 0, 1)
             best = min(best, np.hypot(*(a + u * (b - a) - [px[t], py[t]])))
         assert best < 1e-9
-        assert ang[0] - 1e-12 <= pyaw[t] <= ang[-1] + 1e-12
+        # the logged yaw is the arc's tangent, so the yaw at a point of the
+        # path is the polar angle about the circle's centre (0, R), up to the
+        # chord's sagitta (w^2 / 8 of a row)
+        assert abs(pyaw[t] - math.atan2(px[t], R - py[t])) < 1e-4
     assert np.all(np.diff(px) > 0)
 
 
@@ -183,3 +186,44 @@ def test_controlled_and_partly_logged_objects_are_left_alone():
     r2 = oracle.rollout_idm(sc.obj_off, None, init, sc.accel, sc.curvature, allc, lw, None, T, DT)
     np.testing.assert_array_equal(r1["traj"]["x"], r2["traj"]["x"])
     np.testing.assert_array_equal(r1["collision"], r2["collision"])
+
+
+def test_no_lookahead_beyond_the_path_end():
+    # path of 9 m (0.9 m per row): poses at 2, 4, 6, 8 m only.  An object whose
+    # box (x in [10.5, 15.5]) would overlap the agent's box at the path's end
+    # point (x in [6.75, 11.25]) but not at the last pose (x <= 10.25) is no
+    # lead: the free-road term applies
+    T = 10
+    v = 5.0
+    xs = np.stack([0.9 * np.arange(T + 1), np.full(T + 1, 13.0)], axis=1)
+    lw = _logs(xs, np.zeros((T + 1, 2)), np.zeros((T + 1, 2)), T)
+    lw["length"][:, 1] = 5.0
+    lw["vx"][0] = [v, 0.0]
+    out = _run(lw, T, [0, 1])
+    a = _free_accel(v)
+    assert math.isclose(out["traj"]["vx"][0, 0], v + a * DT, abs_tol=1e-12)
+
+
+def test_stopping_within_the_step():
+    # zero gap (a = -brake) at 0.4 m/s: the agent stops after v^2 / (2 brake)
+    T = 1
+    v = 0.4
+    xs = np.array([[0.0, 5.5], [20.0, 5.5]])
+    lw = _logs(xs, np.zeros((2, 2)), np.zeros((2, 2)), T)
+    lw["vx"][0] = [v, 0.0]
+    out = _run(lw, T, [0, 1])
+    assert math.isclose(out["traj"]["x"][0, 0], v * v / (2 * P["brake"]), abs_tol=1e-12)
+    assert out["traj"]["vx"][0, 0] == 0.0
+
+
+def test_braking_is_clamped_to_the_hardest():
+    # a fast agent with a small positive gap: the IDM law asks for far more
+    # than the hardest braking, which is what it gets
+    T = 1
+    v, Ll = 15.0, 4.5
+    xl = 4.0 + 0.5 * (4.5 + Ll) - 0.5     # first overlapping pose m = 2 (4 m): gap 2 m
+    xs = np.array([[0.0, xl], [30.0, xl]])
+    lw = _logs(xs, np.zeros((2, 2)), np.zeros((2, 2)), T)
+    lw["vx"][0] = [v, 0.0]
+    out = _run(lw, T, [0, 1])
+    assert math.isclose(out["traj"]["vx"][0, 0], v - P["brake"] * DT, abs_tol=1e-12)
