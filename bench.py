@@ -352,6 +352,27 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
                       "output_GBps": out_bytes / (okm * 1e-3) / 1e9}
     log("observe: %.3f ms for %d egos (kernel %.3f ms)" % (oms, S * E, okm))
 
+    # the observation of every step of the fused rollout's trajectory, one launch
+    del idx, rf, of
+    idx = torch.empty((T, S * E * K), dtype=torch.int32, device=dev)
+    rf = torch.empty((T, S * E * K * 4), device=dev)
+    of = torch.empty((T, S * E * ds.batch.max_objects * 8), device=dev)
+    wm.observe_seq(ds.batch, traj2, T, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_OBSERVE)
+    t0 = time.perf_counter()
+    wm.observe_seq(ds.batch, traj2, T, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    sms = 1e3 * (time.perf_counter() - t0)
+    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
+    wm.profile_enable(False)
+    out["observe_seq"] = {"ms": sms, "kernel_ms": kms / max(kl, 1), "rows": T, "egos_per_row": S * E, "k": K,
+                          "ego_steps_per_s": T * S * E / (sms * 1e-3),
+                          "output_GBps": T * out_bytes / (kms / max(kl, 1) * 1e-3) / 1e9}
+    log("observe_seq: %.3f ms for %d steps x %d egos" % (sms, T, S * E))
+    del idx, rf, of
+
     ragged(out, dev)
     idm(out, scene, ds, dev, tune)
     fwd_bwd_config3(out, dev)

@@ -229,6 +229,16 @@ int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
 int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg, const int32_t *ego,
                int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream);
 
+/* The default observation of every step of a state sequence in one launch:
+ * for the paper's per-step observation (Sec. 4.1, step returns the next
+ * observation) of a rollout's trajectory.  st holds T rows [T][n] (row t at
+ * st + t * total_objects, e.g. the traj of wm_rollout); the egos are the same
+ * for every row; row t's outputs follow row t-1's: rg_idx [T][S*E*k],
+ * rg_feat [T][S*E*k*4], obj_feat [T][S*E*max_objects*8], each as in
+ * wm_observe.  T <= 65535.  wm_observe is the case T = 1. */
+int wm_observe_seq(const wm_batch *batch, const wm_state *st, int32_t T, const wm_roadgraph *rg, const int32_t *ego,
+                   int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream);
+
 /* Fused rollout of T steps (Sec. 5.1 Rollout; each step as wm_step with all
  * metrics, evaluated on the successor state).  One persistent kernel runs all
  * T steps of every (scenario, object slice) work unit, taking units from a

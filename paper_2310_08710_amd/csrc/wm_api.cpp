@@ -413,8 +413,8 @@ int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
     return device_status("wm_offroad");
 }
 
-int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg, const int32_t *ego, int32_t E,
-               int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream)
+int wm_observe_seq(const wm_batch *batch, const wm_state *st, int32_t T, const wm_roadgraph *rg, const int32_t *ego,
+                   int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream)
 {
     CHECK(check_batch(batch));
     CHECK(check_state(st, "state"));
@@ -423,21 +423,30 @@ int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
     CHECK(check_rg(rg));
     if (!ego || !rg_idx)
         return fail(WM_ERR_NULL, "ego or rg_idx is NULL");
-    if (E < 1 || k < 1)
-        return fail(WM_ERR_RANGE, "E = %d and k = %d must be >= 1", E, k);
+    if (E < 1 || k < 1 || T < 1)
+        return fail(WM_ERR_RANGE, "E = %d, k = %d and T = %d must be >= 1", E, k, T);
+    if (T > 65535)
+        return fail(WM_ERR_UNSUPPORTED, "T = %d > 65535", T);
     if (k > WM_MAX_TOPK)
         return fail(WM_ERR_UNSUPPORTED, "k = %d > %d", k, WM_MAX_TOPK);
     if (batch->max_rg_points > WM_MAX_OBSERVE_POINTS)
         return fail(WM_ERR_UNSUPPORTED, "max_rg_points = %d > %d", batch->max_rg_points, WM_MAX_OBSERVE_POINTS);
-    if ((long)batch->num_scenarios * E > 0x7fffffffL / (k > 8 ? k : 8))
-        return fail(WM_ERR_UNSUPPORTED, "S * E * k too large");
+    const long long slots = (long long)batch->num_scenarios * E;
+    if (slots * T * (k > 8 ? k : 8) > 0x7fffffffLL || slots * T * batch->max_objects * 8 > 0x7fffffffLL * 4)
+        return fail(WM_ERR_UNSUPPORTED, "T * S * E * k too large");
     wm::ObserveArgs a{batch->obj_off, batch->rg_off, *st, *rg, ego, E, k, batch->max_objects, rg_idx, rg_feat,
-                      obj_feat};
+                      obj_feat, (long)batch->total_objects, (long)batch->num_scenarios};
     {
         ProfScope ps(WM_PROF_OBSERVE, (hipStream_t)stream);
-        wm::launch_observe(*batch, a, (hipStream_t)stream);
+        wm::launch_observe(*batch, a, T, (hipStream_t)stream);
     }
     return device_status("wm_observe");
+}
+
+int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg, const int32_t *ego, int32_t E,
+               int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream)
+{
+    return wm_observe_seq(batch, st, 1, rg, ego, E, k, rg_idx, rg_feat, obj_feat, stream);
 }
 
 static int rollout_checks(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,

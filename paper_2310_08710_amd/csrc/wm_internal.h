@@ -95,12 +95,13 @@ struct RollArgs {
 
 struct ObserveArgs {
     const int32_t *obj_off, *rg_off;
-    wm_state st;
+    wm_state st;            // row 0; row t (grid y) is st + t * n
     wm_roadgraph rg;
     const int32_t *ego;
     int E, k, maxN;
-    int32_t *rg_idx;
+    int32_t *rg_idx;        // outputs of row t follow those of row t - 1
     float *rg_feat, *obj_feat;
+    long n, S;              // state row stride (objects), scenarios
 };
 
 struct BackwardArgs {
@@ -173,7 +174,7 @@ void launch_rollout(const RollArgs &a, int grid, hipStream_t st);
 void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float *L, uint8_t *agent,
                       hipStream_t st);
 void launch_loss_reduce(int S, const int32_t *uoff, const float *lossp, float *loss, hipStream_t st);
-void launch_observe(const wm_batch &b, const ObserveArgs &a, hipStream_t st);
+void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream_t st);
 void launch_backward(const BackwardArgs &a, hipStream_t st);
 
 } // namespace wm

@@ -2,7 +2,7 @@
 // and the k road points nearest to the ego, exact, ascending by
 // (binary32 squared distance, index).
 //
-// One 1024-thread work-group per (scenario, ego).  Each thread keeps up to 32
+// One 1024-thread work-group per (scenario, ego) and state row.  Each thread keeps up to 32
 // keys in registers (points j = tid + 1024 r), so a scenario's road graph is
 // read once per ego.  The k-th smallest key is found by a 3-pass radix select
 // (12 + 12 + 8 bits of the float bits, which order like the values because
@@ -49,8 +49,26 @@ __device__ __forceinline__ int block_exclusive(int v, int *wtot, int *total)
     return off + incl - v;
 }
 
-__global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A)
+__global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A0)
 {
+    // grid y: the state row (time step) observed, with its own outputs
+    ObserveArgs A = A0;
+    if (blockIdx.y > 0) {
+        const long t = blockIdx.y, so = t * A0.n, slots = A0.S * A0.E;
+        A.st.x += so;
+        A.st.y += so;
+        A.st.yaw += so;
+        A.st.vx += so;
+        A.st.vy += so;
+        A.st.length += so;
+        A.st.width += so;
+        A.st.valid += so;
+        A.rg_idx += t * slots * A0.k;
+        if (A.rg_feat)
+            A.rg_feat += t * slots * A0.k * 4;
+        if (A.obj_feat)
+            A.obj_feat += t * slots * A0.maxN * 8;
+    }
     __shared__ int hist[4096];
     __shared__ int wtot[kObsThreads / 64];
     __shared__ uint64_t sel[1024];
@@ -215,9 +233,9 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A)
     }
 }
 
-void launch_observe(const wm_batch &b, const ObserveArgs &a, hipStream_t st)
+void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_observe, dim3(b.num_scenarios * a.E), dim3(kObsThreads), 0, st, a);
+    hipLaunchKernelGGL(k_observe, dim3(b.num_scenarios * a.E, rows), dim3(kObsThreads), 0, st, a);
 }
 
 } // namespace wm

@@ -101,6 +101,8 @@ def lib() -> C.CDLL:
                                  C.POINTER(CTuning), _P, C.c_size_t, _P]
         L.wm_observe.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CRoadgraph), _P, C.c_int32,
                                  C.c_int32, _P, _P, _P, _P]
+        L.wm_observe_seq.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.c_int32, C.POINTER(CRoadgraph), _P,
+                                     C.c_int32, C.c_int32, _P, _P, _P, _P]
         L.wm_rollout.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
                                  C.POINTER(CRoadgraph), C.c_int32, C.c_float, C.c_int32, C.POINTER(CState),
                                  C.POINTER(CState), C.POINTER(CMetrics), _P, C.POINTER(CTuning), _P, C.c_size_t, _P]
@@ -335,6 +337,16 @@ def observe(batch: Batch, st: State, rg: Roadgraph, ego: torch.Tensor, E: int, k
     b, s, r = batch.c(), st.c(), rg.c()
     _check(lib().wm_observe(C.byref(b), C.byref(s), C.byref(r), ego.data_ptr(), E, k, rg_idx.data_ptr(),
                             _ptr(rg_feat), _ptr(obj_feat), _stream(stream)))
+
+
+def observe_seq(batch: Batch, traj: State, T: int, rg: Roadgraph, ego: torch.Tensor, E: int, k: int,
+                rg_idx: torch.Tensor, rg_feat: Optional[torch.Tensor] = None, obj_feat: Optional[torch.Tensor] = None,
+                stream=None):
+    """Observation of every row of a [T, n] state sequence in one launch;
+    outputs are [T, ...] with each row as in observe()."""
+    b, st, r = batch.c(), traj.c(), rg.c()
+    _check(lib().wm_observe_seq(C.byref(b), C.byref(st), T, C.byref(r), ego.data_ptr(), E, k, rg_idx.data_ptr(),
+                                _ptr(rg_feat), _ptr(obj_feat), _stream(stream)))
 
 
 def rollout(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: Optional[Roadgraph], T: int, dt: float,

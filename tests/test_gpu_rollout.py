@@ -223,3 +223,47 @@ def test_observe_topk_and_frames(k):
     ok = within(g_of, o_of)
     ok[..., 2] = np.abs(((g_of[..., 2] - o_of[..., 2] + math.pi) % (2 * math.pi)) - math.pi) <= 1e-5
     assert ok.all()
+
+
+def test_observe_every_step_of_a_sequence():
+    """wm_observe_seq over the logged rows equals the oracle's observation of
+    each row (indices bit-exact); over a fused rollout's trajectory it equals
+    one wm_observe call per row."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    k = 200
+    sc = synth.make_scene(4, scenarios=3, objects=(4, 40), rg_points=(700, 3000), steps=6, rg_invalid_frac=0.05,
+                          invalid_frac=0.1)
+    ds = wm.upload(sc, dev)
+    S, E = sc.num_scenarios, sc.ego.shape[1]
+    maxN, n, T = ds.batch.max_objects, sc.total_objects, sc.steps
+    R = T + 1
+    idx = torch.empty((R, S * E * k), dtype=torch.int32, device=dev)
+    rf = torch.empty((R, S * E * k * 4), device=dev)
+    of = torch.empty((R, S * E * maxN * 8), device=dev)
+    wm.observe_seq(ds.batch, ds.log_seq, R, ds.rg, ds.ego, E, k, idx, rf, of)
+    torch.cuda.synchronize()
+    lw = sc.log_window()
+    for t in range(R):
+        o_idx, o_rf, o_of = oracle.observe(sc.obj_off, sc.rg_off, f64({q: v[t] for q, v in lw.items()}), f64(sc.rg),
+                                           sc.ego, k, maxN)
+        np.testing.assert_array_equal(idx[t].cpu().numpy().reshape(S, E, k), o_idx, err_msg="row %d" % t)
+        assert within(rf[t].cpu().numpy().reshape(S, E, k, 4), o_rf).all(), t
+        g_of = of[t].cpu().numpy().reshape(S, E, maxN, 8)
+        ok = within(g_of, o_of)
+        ok[..., 2] = np.abs(((g_of[..., 2] - o_of[..., 2] + math.pi) % (2 * math.pi)) - math.pi) <= 1e-5
+        assert ok.all(), t
+    # the rollout's own trajectory: one launch equals one call per row
+    ws = ds.batch.workspace(T, 0)
+    traj = wm.State.empty((T, n), dev)
+    wm.rollout(ds.batch, ds.init, ds.act_seq, ds.log_seq, ds.rg, T, sc.dt, ws, traj=traj)
+    idx2 = torch.empty((T, S * E * k), dtype=torch.int32, device=dev)
+    of2 = torch.empty((T, S * E * maxN * 8), device=dev)
+    wm.observe_seq(ds.batch, traj, T, ds.rg, ds.ego, E, k, idx2, None, of2)
+    one = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
+    of1 = torch.empty((S * E * maxN * 8,), device=dev)
+    for t in range(T):
+        wm.observe(ds.batch, traj.row(t), ds.rg, ds.ego, E, k, one, None, of1)
+        torch.cuda.synchronize()
+        assert torch.equal(one, idx2[t]) and torch.equal(of1, of2[t]), t
