@@ -252,6 +252,13 @@ __device__ __forceinline__ float candidate_band(float qqmax, float cx, float cy)
 // Bytes of the per-wave LDS stage of the scan (one chunk).
 constexpr int kStageBytes = kChunkFloats * 4;
 
+// Position of point j's qq in its chunk's qq column: rotated by one within
+// each group of four.  A 16-byte LDS read puts component c of a group in a
+// register of VGPR bank c, so point j's x (component j % 4) and its qq
+// (component (j + 1) % 4) come from different banks and the FMA that reads
+// both does not stall on a bank conflict.
+__host__ __device__ constexpr int qq_slot(int j) { return (j & ~3) | ((j + 1) & 3); }
+
 // Minimum of T over one chunk already staged in LDS (x, y, qq columns),
 // folded into m.  All lanes read the same addresses (LDS broadcast reads of
 // four points per column); the points are VGPR operands of the FMAs.
@@ -264,10 +271,11 @@ __device__ __forceinline__ void fold_chunk(const float4 *stage, const float (&m2
         const float4 X = stage[j4], Y = stage[kChunk / 4 + j4], Q = stage[kChunk / 2 + j4];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float t0 = __builtin_fmaf(m2y[r], Y.x, __builtin_fmaf(m2x[r], X.x, Q.x));
-            const float t1 = __builtin_fmaf(m2y[r], Y.y, __builtin_fmaf(m2x[r], X.y, Q.y));
-            const float t2 = __builtin_fmaf(m2y[r], Y.z, __builtin_fmaf(m2x[r], X.z, Q.z));
-            const float t3 = __builtin_fmaf(m2y[r], Y.w, __builtin_fmaf(m2x[r], X.w, Q.w));
+            // Q holds the group's qq rotated by one (qq_slot)
+            const float t0 = __builtin_fmaf(m2y[r], Y.x, __builtin_fmaf(m2x[r], X.x, Q.y));
+            const float t1 = __builtin_fmaf(m2y[r], Y.y, __builtin_fmaf(m2x[r], X.y, Q.z));
+            const float t2 = __builtin_fmaf(m2y[r], Y.z, __builtin_fmaf(m2x[r], X.z, Q.w));
+            const float t3 = __builtin_fmaf(m2y[r], Y.w, __builtin_fmaf(m2x[r], X.w, Q.x));
             m[r] = fminf(fminf(m[r], t0), t1);
             m[r] = fminf(fminf(m[r], t2), t3);
         }
@@ -335,7 +343,7 @@ __device__ __forceinline__ void scan_edges(const float *__restrict__ stream, int
 // minimum of D over the chunk's real points (index < E), folded into
 // (best, bidx) with strict <, so chunks rescanned in ascending order keep the
 // lowest index.  The chunk's x and y columns arrive as 16-byte vector loads
-// issued together (chunks are 16-byte aligned in the workspace).
+// (chunks are 16-byte aligned in the workspace).
 __device__ __forceinline__ void rescan_chunk(const float *__restrict__ stream, int c, int E, float cx, float cy,
                                              float &best, int &bidx)
 {
@@ -356,37 +364,6 @@ __device__ __forceinline__ void rescan_chunk(const float *__restrict__ stream, i
             }
         }
     }
-}
-
-// Exact scan of every chunk for one corner by a whole wave (the corner is
-// wave-uniform): lane l takes points l, l + 64, ... of each chunk, then a
-// wave reduction on (D, index) keeps the lowest index of the minimum.
-// Returns the point index (or -1) in every lane.
-__device__ __forceinline__ int wave_full_scan(const float *__restrict__ stream, int nch, int E, float cx, float cy)
-{
-    const int lane = threadIdx.x & 63;
-    float best = __builtin_inff();
-    int bj = 0x7fffffff;
-    for (int c = 0; c < nch; ++c) {
-        const float *p = stream + kChunkFloats * c;
-        for (int h = lane; h < kChunk; h += 64) {
-            const int j = kChunk * c + h;
-            const float d = edge_d2(p[h], p[kChunk + h], cx, cy);
-            if (j < E && d < best) {
-                best = d;
-                bj = j;
-            }
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        const float ob = __shfl_xor(best, o);
-        const int oj = __shfl_xor(bj, o);
-        if (ob < best || (ob == best && oj < bj)) {
-            best = ob;
-            bj = oj;
-        }
-    }
-    return bj == 0x7fffffff ? -1 : bj;
 }
 
 } // namespace wm

@@ -26,7 +26,8 @@ __host__ __device__ inline long edge_base(int rg_off_s, int s)
 // from edge_base(rg_off[s], s): its valid road edges in index order, padded
 // to whole chunks (two spare chunks at the end of the arrays let the scan
 // prefetch past the last chunk).  `stream` holds chunk c
-// of that range as x[128], y[128], qq[128] (qq = x^2 + y^2; padding points have
+// of that range as x[128], y[128], qq[128] (qq = x^2 + y^2, rotated within
+// groups of four, see qq_slot in wm_device.h; padding points have
 // x = y = 0 and qq = +inf); `dir` and `idx` (scenario-local original index)
 // are indexed by point.  `count` = edges per scenario, `qqmax` = their max qq.
 struct Edges {

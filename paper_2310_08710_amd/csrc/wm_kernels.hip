@@ -62,10 +62,10 @@ __global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict_
             const int o = off + pre;
             const float x = rg.x[j], y = rg.y[j];
             const float qq = __builtin_fmaf(y, y, x * x);
-            float *ch = stream + kChunkFloats * (o / kChunk) + (o % kChunk);
-            ch[0] = x;
-            ch[kChunk] = y;
-            ch[2 * kChunk] = qq;
+            float *ch = stream + kChunkFloats * (o / kChunk);
+            ch[o % kChunk] = x;
+            ch[kChunk + o % kChunk] = y;
+            ch[2 * kChunk + qq_slot(o % kChunk)] = qq;
             E.dir[base + o] = make_float2(rg.dir_x[j], rg.dir_y[j]);
             E.idx[base + o] = j - p0;
             my_max = fmaxf(my_max, qq);
@@ -79,10 +79,10 @@ __global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict_
     const int cnt = run;
     const int padded = (cnt + kChunk - 1) / kChunk * kChunk;
     for (int o = cnt + threadIdx.x; o < padded; o += BT) {
-        float *ch = stream + kChunkFloats * (o / kChunk) + (o % kChunk);
-        ch[0] = 0.f;
-        ch[kChunk] = 0.f;
-        ch[2 * kChunk] = __builtin_inff();
+        float *ch = stream + kChunkFloats * (o / kChunk);
+        ch[o % kChunk] = 0.f;
+        ch[kChunk + o % kChunk] = 0.f;
+        ch[2 * kChunk + qq_slot(o % kChunk)] = __builtin_inff();
         E.dir[base + o] = make_float2(0.f, 0.f);
         E.idx[base + o] = -1;
     }
@@ -301,7 +301,9 @@ __device__ __forceinline__ void scan_r(const float *stream, int c0, int c1, floa
 // Waves: w = tid / 64, corner wave cw = w % CW (256 corner slots each), edge
 // split g = w / CW (contiguous chunk ranges in index order).  Leaves sk[slot]
 // and nidx[slot] (scenario-local point index or -1) for slot < 4*Ns.
-// Contains two block barriers.
+// Contains two block barriers, plus two per corner that needs the exact scan
+// of every point (their count is read by every thread after a barrier, so
+// the barriers are uniform).
 __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
                              const float2 *__restrict__ edir, const int32_t *__restrict__ eidx, int E, float qqmax,
                              int G, int CW, ScanLds C, float *sk, int *nidx)
@@ -390,7 +392,7 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
             float best = __builtin_inff();
             int bj = -1;
             if (full) {
-                // rare: left to a whole wave after the next barrier
+                // rare: left to the whole work-group after the next barrier
                 C.full[atomicAdd(C.nfull, 1)] = slot;
             } else {
                 const int lo = other >= 0 ? min(bc, other) : bc;
@@ -410,21 +412,54 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
         nidx[slot] = near;
     }
     __syncthreads();
+    // corners with three or more candidate chunks (rare): an exact scan of
+    // every edge point by the whole work-group, one corner at a time, with a
+    // reduction on (D, index) that keeps the lowest index of the minimum
     const int nf = *C.nfull;
-    if (nf > 0) {
-        const int nw = blockDim.x >> 6;
-        for (int f = w; f < nf; f += nw) {
-            const int slot = C.full[f];
-            const int o = i0 + (slot >> 2);
-            float x, y;
-            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
-            const int bj = wave_full_scan(stream, nch, E, x, y);
-            if (lane == 0 && bj >= 0) {
-                const float *ch = stream + kChunkFloats * (bj / kChunk) + (bj % kChunk);
+    const int nthr = blockDim.x, nw = nthr >> 6;
+    for (int f = 0; f < nf; ++f) {
+        const int slot = C.full[f];
+        const int o = i0 + (slot >> 2);
+        float x, y;
+        box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+        float best = __builtin_inff();
+        int bj = 0x7fffffff;
+        for (int j = tid; j < E; j += nthr) {
+            const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
+            const float d = edge_d2(ch[0], ch[kChunk], x, y);
+            if (d < best) {      // j ascends per thread: strict < keeps the lowest
+                best = d;
+                bj = j;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const float ob = __shfl_xor(best, off);
+            const int oj = __shfl_xor(bj, off);
+            if (ob < best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        // the merge lists are free after the first barrier: wave results there
+        if (lane == 0) {
+            C.b1[w] = best;
+            C.i1[w] = bj;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            float b = __builtin_inff();
+            int j = 0x7fffffff;
+            for (int v = 0; v < nw; ++v)
+                if (C.b1[v] < b || (C.b1[v] == b && C.i1[v] < j)) {
+                    b = C.b1[v];
+                    j = C.i1[v];
+                }
+            if (j != 0x7fffffff) {
+                const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
                 const float qx = ch[0], qy = ch[kChunk];
-                const float2 d = edir[bj];
+                const float2 d = edir[j];
                 sk[slot] = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
-                nidx[slot] = eidx[bj];
+                nidx[slot] = eidx[j];
             }
         }
         __syncthreads();
