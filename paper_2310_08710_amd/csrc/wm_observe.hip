@@ -5,7 +5,7 @@
 // One 1024-thread work-group per (scenario, ego) and state row.  Each thread keeps up to 32
 // keys in registers (points j = tid + 1024 r), so a scenario's road graph is
 // read once per ego.  The k-th smallest key is found by a 3-pass radix select
-// (12 + 12 + 8 bits of the float bits, which order like the values because
+// (11 + 11 + 10 bits of the float bits, which order like the values because
 // the keys are non-negative) with LDS histograms; the points with a smaller
 // key plus the lowest-index points equal to it are compacted and sorted by a
 // bitonic network on (key << 32 | index).
@@ -17,6 +17,8 @@ namespace wm {
 constexpr int kObsThreads = 1024;
 constexpr int kObsKeys = WM_MAX_OBSERVE_POINTS / kObsThreads;  // 32
 constexpr uint32_t kNoKey = 0xffffffffu;                        // invalid point / padding
+constexpr int kHistBins = 2048;                                 // widest radix digit: 11 bits
+constexpr int kHistCopies = 4;
 
 __device__ __forceinline__ uint32_t topk_key(float qx, float qy, float ex, float ey)
 {
@@ -69,7 +71,9 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A0)
         if (A.obj_feat)
             A.obj_feat += t * slots * A0.maxN * 8;
     }
-    __shared__ int hist[4096];
+    // four copies of the radix histogram, lane l counting into copy l % 4,
+    // so that lanes of one wave with equal digits do not all hit one address
+    __shared__ int hist[kHistCopies * kHistBins];
     __shared__ int wtot[kObsThreads / 64];
     __shared__ uint64_t sel[1024];
     __shared__ int sh_bin, sh_before, sh_count;
@@ -126,36 +130,42 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A0)
     // ---- radix select of the kk-th smallest key (rank kk-1) ----
     uint32_t prefix = 0, pmask = 0;
     int rank = kk - 1;
-    const int shifts[3] = {20, 8, 0};
-    const int widths[3] = {12, 12, 8};
+    const int shifts[3] = {21, 10, 0};
+    const int widths[3] = {11, 11, 10};
+    int *myhist = hist + kHistBins * (tid & (kHistCopies - 1));
     for (int pass = 0; pass < 3 && kk > 0; ++pass) {
         const int sh = shifts[pass], nb = 1 << widths[pass];
-        for (int b = tid; b < nb; b += kObsThreads)
+        for (int b = tid; b < kHistCopies * kHistBins; b += kObsThreads)
             hist[b] = 0;
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kObsKeys; ++r)
             if (key[r] != kNoKey && (key[r] & pmask) == prefix)
-                atomicAdd(&hist[(key[r] >> sh) & (nb - 1)], 1);
+                atomicAdd(&myhist[(key[r] >> sh) & (nb - 1)], 1);
         __syncthreads();
-        // find the bin holding `rank`: per-thread bin groups, then a block scan
+        // find the bin holding `rank`: per-thread bin groups (copies summed),
+        // then a block scan
         const int per = nb / kObsThreads > 0 ? nb / kObsThreads : 1;
-        int cnt = 0;
         const int b0 = tid * per;
+        int cnt = 0;
         if (b0 < nb)
             for (int b = b0; b < b0 + per; ++b)
-                cnt += hist[b];
+                for (int c = 0; c < kHistCopies; ++c)
+                    cnt += hist[kHistBins * c + b];
         int total;
         int before = block_exclusive(b0 < nb ? cnt : 0, wtot, &total);
         if (b0 < nb && rank >= before && rank < before + cnt) {
             int acc = before;
             for (int b = b0; b < b0 + per; ++b) {
-                if (rank < acc + hist[b]) {
+                int hb = 0;
+                for (int c = 0; c < kHistCopies; ++c)
+                    hb += hist[kHistBins * c + b];
+                if (rank < acc + hb) {
                     sh_bin = b;
                     sh_before = acc;
                     break;
                 }
-                acc += hist[b];
+                acc += hb;
             }
         }
         __syncthreads();
@@ -167,27 +177,43 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A0)
     const uint32_t kth = prefix;   // the kk-th smallest key (when kk > 0)
 
     // ---- compaction: keys < kth, then the lowest-index keys == kth ----
-    int nless_local = 0;
+    int nless_local = 0, nle_local = 0;
 #pragma unroll
-    for (int r = 0; r < kObsKeys; ++r)
-        nless_local += (kk > 0 && key[r] < kth);
-    int nless;
-    (void)block_exclusive(nless_local, wtot, &nless);
-    const int need_eq = kk - nless;
-    if (tid == 0)
-        sh_count = 0;
-    __syncthreads();
-    int eq_seen = 0;   // equal keys at lower index, summed over earlier rounds
     for (int r = 0; r < kObsKeys; ++r) {
-        const bool eq = kk > 0 && key[r] == kth;
-        int tot;
-        const int ex_rank = block_exclusive(eq ? 1 : 0, wtot, &tot);
-        const bool take = (kk > 0 && key[r] < kth) || (eq && eq_seen + ex_rank < need_eq);
-        if (take) {
-            const int pos = atomicAdd(&sh_count, 1);
-            sel[pos] = ((uint64_t)key[r] << 32) | (uint32_t)(tid + kObsThreads * r);
+        nless_local += (kk > 0 && key[r] < kth);
+        nle_local += (kk > 0 && key[r] <= kth);
+    }
+    int nless, nle;
+    (void)block_exclusive(nless_local, wtot, &nless);
+    const int le_before = block_exclusive(nle_local, wtot, &nle);
+    const int need_eq = kk - nless;
+    if (nle == kk) {
+        // no tie to break at the k-th key: every key <= kth is selected; each
+        // thread writes its keys at its exclusive prefix (order is irrelevant:
+        // the list is sorted below)
+        int pos = le_before;
+#pragma unroll
+        for (int r = 0; r < kObsKeys; ++r)
+            if (kk > 0 && key[r] <= kth)
+                sel[pos++] = ((uint64_t)key[r] << 32) | (uint32_t)(tid + kObsThreads * r);
+    } else {
+        // more keys equal the k-th than are needed: the lowest indices win,
+        // ranked in index order (j = tid + 1024 r) one round r at a time
+        if (tid == 0)
+            sh_count = 0;
+        __syncthreads();
+        int eq_seen = 0;   // equal keys at lower index, summed over earlier rounds
+        for (int r = 0; r < kObsKeys; ++r) {
+            const bool eq = kk > 0 && key[r] == kth;
+            int tot;
+            const int ex_rank = block_exclusive(eq ? 1 : 0, wtot, &tot);
+            const bool take = (kk > 0 && key[r] < kth) || (eq && eq_seen + ex_rank < need_eq);
+            if (take) {
+                const int pos = atomicAdd(&sh_count, 1);
+                sel[pos] = ((uint64_t)key[r] << 32) | (uint32_t)(tid + kObsThreads * r);
+            }
+            eq_seen += tot;
         }
-        eq_seen += tot;
     }
     __syncthreads();
     // pad to a power of two and sort ascending
