@@ -530,9 +530,9 @@ static int rollout_impl(const wm_batch *batch, const wm_state *init, const wm_ac
     if (idm) {
         a.has_idm = 1;
         a.idm = *idm;
-        a.idmL = (const float *)(w + L.idmL);
+        a.idmP = (const float4 *)(w + L.idmP);
         a.idmA = (const uint8_t *)(w + L.idmA);
-        wm::launch_idm_paths(batch->total_objects, T, *log_seq, act_seq->controlled, (float *)(w + L.idmL),
+        wm::launch_idm_paths(batch->total_objects, T, *log_seq, act_seq->controlled, (float4 *)(w + L.idmP),
                              (uint8_t *)(w + L.idmA), s);
     }
     const int U = 64 * tn.CW;

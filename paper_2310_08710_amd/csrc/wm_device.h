@@ -119,33 +119,35 @@ __device__ __forceinline__ float sat_margin(const Box &a, const Box &b)
 // lengths L (time-major [T+1][n] like the logs).
 // ---------------------------------------------------------------------------
 
-// Pose at arc length s on the path of object g: linear between the rows k-1
-// and k around the first k with L_k > s (yaw along the shorter arc between the
-// logged yaws), or row T's pose when there is no such row.
-__device__ __forceinline__ void idm_pose(const wm_state &log, const float *__restrict__ L, long n, int T, long g,
-                                         float s, float &x, float &y, float &yaw)
+// An IDM agent's path, object-major: row k of object g is path[g * (T + 1)
+// + k] = (x, y, yaw, L) of its logged state k, L the cumulative arc length.
+// Pose at arc length s: linear between the rows k-1 and k around the first k
+// with L_k > s (yaw along the shorter arc between the logged yaws), or row
+// T's pose when there is no such row.  One path is 16 (T + 1) contiguous
+// bytes, so the search and the interpolation stay in a few cache lines.
+__device__ __forceinline__ void idm_pose(const float4 *__restrict__ path, int T, float s, float &x, float &y,
+                                         float &yaw)
 {
     int lo = 1, hi = T + 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (L[(long)mid * n + g] > s)
+        if (path[mid].w > s)
             hi = mid;
         else
             lo = mid + 1;
     }
     if (lo > T) {
-        const long r = (long)T * n + g;
-        x = log.x[r];
-        y = log.y[r];
-        yaw = log.yaw[r];
+        const float4 r = path[T];
+        x = r.x;
+        y = r.y;
+        yaw = r.z;
         return;
     }
-    const long a = (long)(lo - 1) * n + g, b = (long)lo * n + g;
-    const float La = L[a];
-    const float lam = (s - La) / (L[b] - La);
-    x = __builtin_fmaf(lam, log.x[b] - log.x[a], log.x[a]);
-    y = __builtin_fmaf(lam, log.y[b] - log.y[a], log.y[a]);
-    yaw = __builtin_fmaf(lam, wrap_angle(log.yaw[b] - log.yaw[a]), log.yaw[a]);
+    const float4 a = path[lo - 1], b = path[lo];
+    const float lam = (s - a.w) / (b.w - a.w);
+    x = __builtin_fmaf(lam, b.x - a.x, a.x);
+    y = __builtin_fmaf(lam, b.y - a.y, a.y);
+    yaw = __builtin_fmaf(lam, wrap_angle(b.z - a.z), a.z);
 }
 
 // IDM acceleration for speed v; `lead` selects the interaction term with gap

@@ -86,11 +86,11 @@ struct RollArgs {
     const int32_t *uoff;
     const int2 *units;
     int32_t *counter;
-    // IDM sim agents (has_idm): parameters, path arc lengths [T+1][n] and
-    // the per-object agent flags
+    // IDM sim agents (has_idm): parameters, the object-major paths
+    // [n][T+1] of (x, y, yaw, arc length) and the per-object agent flags
     int has_idm;
     wm_idm idm;
-    const float *idmL;
+    const float4 *idmP;
     const uint8_t *idmA;
 };
 
@@ -120,7 +120,7 @@ struct BackwardArgs {
 
 // Workspace sections (byte offsets, each 256-aligned).
 struct WsLayout {
-    size_t ecount, stream, edir, eidx, qqmax, uoff, units, lossp, counter, seg, idmL, idmA, total;
+    size_t ecount, stream, edir, eidx, qqmax, uoff, units, lossp, counter, seg, idmP, idmA, total;
 };
 
 inline WsLayout ws_layout(int S, int n, int P, int T, int K)
@@ -139,7 +139,7 @@ inline WsLayout ws_layout(int S, int n, int P, int T, int K)
     L.lossp = take(sizeof(float) * ((size_t)n + 1));
     L.counter = take(sizeof(int32_t) * 16);
     L.seg = (T > 0 && K > 0) ? take(sizeof(float) * 5 * (size_t)(K + 1) * (size_t)n) : o;
-    L.idmL = T > 0 ? take(sizeof(float) * (size_t)(T + 1) * (size_t)n) : o;
+    L.idmP = T > 0 ? take(sizeof(float) * 4 * (size_t)(T + 1) * (size_t)n) : o;
     L.idmA = T > 0 ? take((size_t)n + 1) : o;
     L.total = o;
     return L;
@@ -172,7 +172,7 @@ void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st);
 size_t rollout_lds_bytes(int maxN, int G, int CW);
 int rollout_grid(int G, int CW, int maxN, int n_units_bound);
 void launch_rollout(const RollArgs &a, int grid, hipStream_t st);
-void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float *L, uint8_t *agent,
+void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float4 *path, uint8_t *agent,
                       hipStream_t st);
 void launch_loss_reduce(int S, const int32_t *uoff, const float *lossp, float *loss, hipStream_t st);
 void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream_t st);

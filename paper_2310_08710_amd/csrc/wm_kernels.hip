@@ -682,7 +682,7 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
         lk[i] = 0x7fffffff;
         if (use_mask && agent[i]) {
             float yaw;
-            idm_pose(A.log, A.idmL, n, A.T, o0 + i, sig[i], pc[2 * i], pc[2 * i + 1], yaw);
+            idm_pose(A.idmP + (long)(o0 + i) * (A.T + 1), A.T, sig[i], pc[2 * i], pc[2 * i + 1], yaw);
         }
     }
     if (use_mask)
@@ -709,10 +709,11 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
             continue;
         const long g = o0 + i;
         const float sm = __builtin_fmaf((float)m, A.idm.lookahead_step, sig[i]);
-        if (sm > A.idmL[(long)A.T * n + g])
+        const float4 *path = A.idmP + g * (A.T + 1);
+        if (sm > path[A.T].w)
             continue;
         float px, py, pyaw, ps, pcs;
-        idm_pose(A.log, A.idmL, n, A.T, g, sm, px, py, pyaw);
+        idm_pose(path, A.T, sm, px, py, pyaw);
         sincosf(pyaw, &ps, &pcs);
         const Box a{px, py, pcs, ps, 0.5f * L.len[i], 0.5f * L.wid[i]};
         const float ra = 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i]));
@@ -773,7 +774,8 @@ __device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int
         adv = v * v / (2.0f * -a);
         vn = 0.f;
     }
-    const float Lend = A.idmL[(long)A.T * A.n + g];
+    const float4 *path = A.idmP + g * (A.T + 1);
+    const float Lend = path[A.T].w;
     if (sig[i] + adv >= Lend) {   // the end of the path: halt there
         sig[i] = Lend;
         vn = 0.f;
@@ -781,7 +783,7 @@ __device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int
         sig[i] += adv;
     }
     float x, y, yaw, sn, cs;
-    idm_pose(A.log, A.idmL, A.n, A.T, g, sig[i], x, y, yaw);
+    idm_pose(path, A.T, sig[i], x, y, yaw);
     sincosf(yaw, &sn, &cs);
     L.x[i] = x;
     L.y[i] = y;
@@ -795,22 +797,24 @@ __device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int
     L.valid[i] = A.log.valid[row + g];
 }
 
-// Arc lengths of every object's logged path, rows 0..T (time-major), and the
-// IDM agent flag: uncontrolled and valid in every row.
+// The logged path of every object, rows 0..T, object-major as (x, y, yaw,
+// cumulative arc length), and the IDM agent flag: uncontrolled and valid in
+// every row.
 __global__ __launch_bounds__(256) void k_idm_paths(int n, int T, wm_state log, const uint8_t *__restrict__ controlled,
-                                                   float *__restrict__ Lout, uint8_t *__restrict__ agent)
+                                                   float4 *__restrict__ path, uint8_t *__restrict__ agent)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n)
         return;
+    float4 *p = path + (long)g * (T + 1);
     bool ok = !controlled[g] && log.valid[g];
     float acc = 0.f;
-    Lout[g] = 0.f;
+    p[0] = make_float4(log.x[g], log.y[g], log.yaw[g], 0.f);
     for (int k = 1; k <= T; ++k) {
         const long a = (long)(k - 1) * n + g, b = (long)k * n + g;
         const float dx = log.x[b] - log.x[a], dy = log.y[b] - log.y[a];
         acc = acc + sqrtf(__builtin_fmaf(dy, dy, dx * dx));
-        Lout[b] = acc;
+        p[k] = make_float4(log.x[b], log.y[b], log.yaw[b], acc);
         ok = ok && log.valid[b];
     }
     agent[g] = (uint8_t)ok;
@@ -1038,10 +1042,10 @@ size_t rollout_lds_bytes(int maxN, int G, int CW)
     return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up(idm, 16);
 }
 
-void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float *L, uint8_t *agent,
+void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float4 *path, uint8_t *agent,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_idm_paths, dim3((n + 255) / 256), dim3(256), 0, st, n, T, log, controlled, L, agent);
+    hipLaunchKernelGGL(k_idm_paths, dim3((n + 255) / 256), dim3(256), 0, st, n, T, log, controlled, path, agent);
 }
 
 int rollout_grid(int G, int CW, int maxN, int n_units_bound)
