@@ -228,7 +228,8 @@ void launch_backward(const BackwardArgs &a, hipStream_t st)
 {
     const size_t lds = backward_lds(a.maxN);
     if (lds > 65536)
-        hipFuncSetAttribute((const void *)k_rollout_backward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // a failure here makes the launch below fail, which the caller reports
+        (void)hipFuncSetAttribute((const void *)k_rollout_backward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_rollout_backward, dim3(a.S), dim3(kBwdThreads), lds, st, a);
 }
 

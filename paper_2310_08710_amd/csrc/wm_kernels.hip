@@ -674,7 +674,6 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
                                           int *lk, const uint8_t *agent, float *pc, uint32_t *mask)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const long n = A.n;
     const int M = A.idm.lookahead_poses;
     const bool use_mask = A.maxN <= kIdmMaskMaxN;
     const int W = (N + 31) >> 5;
@@ -1019,7 +1018,8 @@ void launch_overlap(const wm_batch &b, const OverlapArgs &a, hipStream_t st)
     const size_t lds = objects_lds(a.maxN) + 256 * sizeof(float);
     const int slices = (b.max_objects + a.U - 1) / a.U;
     if (lds > 65536)
-        hipFuncSetAttribute((const void *)k_overlap, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // a failure here makes the launch below fail, which the caller reports
+        (void)hipFuncSetAttribute((const void *)k_overlap, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_overlap, dim3(b.num_scenarios, slices), dim3(256), lds, st, a);
 }
 
@@ -1030,7 +1030,8 @@ void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
     const size_t lds = objects_lds(64 * a.CW) + offroad_scratch(a.G, a.CW);
     const int slices = (b.max_objects + 64 * a.CW - 1) / (64 * a.CW);
     if (lds > 65536)
-        hipFuncSetAttribute((const void *)k_offroad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // a failure here makes the launch below fail, which the caller reports
+        (void)hipFuncSetAttribute((const void *)k_offroad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_offroad, dim3(b.num_scenarios, slices), dim3(64 * a.CW * a.G), lds, st, a);
 }
 

@@ -39,9 +39,13 @@ def _gpu_idm(sc, idm=None, controlled=None):
     return ds, traj, met
 
 
-@pytest.mark.parametrize("seed", [1000, 3000])
-def test_idm_rollout_matches_oracle(seed):
-    sc = _scene(seed)
+@pytest.mark.parametrize("seed,large", [(1000, False), (3000, False), (5000, True)])
+def test_idm_rollout_matches_oracle(seed, large):
+    # large: scenarios above 256 objects take the lead search without the
+    # per-agent candidate masks
+    sc = _scene(seed) if not large else synth.make_scene(
+        2, seed_base=seed, scenarios=2, objects=(260, 300), rg_points=(2000, 3000), steps=12,
+        controlled_per_scenario=4, object_box=120.0, invalid_frac=0.05)
     _, traj, met = _gpu_idm(sc)
     T, n = sc.steps, sc.total_objects
     lw = f64(sc.log_window())
