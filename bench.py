@@ -172,12 +172,19 @@ def main():
     torch.cuda.synchronize()
     wm.profile_enable(True)
     wm.profile_collect(wm.PROF_ROLLOUT)
+    # HIP events between the steps on the stream the steps run on give the
+    # per-step distribution; the wall clock over all K steps gives `value`
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for i in range(args.steps):
         step()
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    step_ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
     kms, launches = wm.profile_collect(wm.PROF_ROLLOUT)
     wm.profile_enable(False)
     valid_objs = int(scene.log["valid"][synth.T0].sum())
@@ -198,6 +205,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "step_ms_median": step_ms[len(step_ms) // 2],
+        "step_ms_min": step_ms[0],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

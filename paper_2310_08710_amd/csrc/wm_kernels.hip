@@ -424,12 +424,24 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
         box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
         float best = __builtin_inff();
         int bj = 0x7fffffff;
-        for (int j = tid; j < E; j += nthr) {
-            const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
-            const float d = edge_d2(ch[0], ch[kChunk], x, y);
-            if (d < best) {      // j ascends per thread: strict < keeps the lowest
-                best = d;
-                bj = j;
+        // eight points per thread per round, loaded together before use
+        for (int j0 = tid; j0 < E; j0 += 8 * nthr) {
+            float px[8], py[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = min(j0 + u * nthr, E - 1);
+                const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
+                px[u] = ch[0];
+                py[u] = ch[kChunk];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u * nthr;
+                const float d = edge_d2(px[u], py[u], x, y);
+                if (j < E && d < best) {   // j ascends per thread: strict < keeps the lowest
+                    best = d;
+                    bj = j;
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
