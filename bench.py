@@ -276,7 +276,8 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
     pms = 1e3 * (time.perf_counter() - t0) / reps
     fused_ms = out["ms_per_step"]
     out["plain"] = {"value": n * T / (pms * 1e-3), "unit": "agent-steps/s", "ms_per_rollout": pms,
-                    "form": "per-step launches (dynamics, overlap, edge compaction, off-road) in one HIP graph",
+                    "form": "per-step launches (dynamics, overlap, edge compaction, off-road) in one HIP graph; "
+                            "the stateless step compacts the road edges every step",
                     "fused_speedup": pms / fused_ms}
     log("plain graph: %.3f ms/rollout (fused speedup %.2fx)" % (pms, pms / fused_ms))
     del g
