@@ -157,6 +157,20 @@ int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act,
             const wm_state *log_next, const wm_roadgraph *rg, float dt, wm_state *next,
             wm_metrics *m, void *ws, size_t ws_bytes, void *stream);
 
+/* Step-by-step simulation with a fixed road graph (closed-loop use, Sec. 4.1):
+ * wm_roadgraph_prepare compacts the road edges of `rg` into `ws` once (the
+ * first part of every off-road computation, which wm_step repeats at each
+ * call); wm_step_prepared is wm_step without that compaction.  Precondition
+ * of wm_step_prepared: the last compaction into `ws` (by
+ * wm_roadgraph_prepare, wm_step, wm_offroad or wm_rollout) was of the same
+ * batch and road graph, which have not changed since; otherwise its
+ * off-road outputs are undefined (no fault: every index stays inside the
+ * workspace).  Workspace: wm_workspace_bytes(batch, 0, 0). */
+int wm_roadgraph_prepare(const wm_batch *batch, const wm_roadgraph *rg, void *ws, size_t ws_bytes, void *stream);
+int wm_step_prepared(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+                     const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *metrics, void *ws,
+                     size_t ws_bytes, void *stream);
+
 /* Expert action by inverse kinematics (App. A.1, inverse kinematics
  * equation; Sec. 5.2 Expert): a = (|v'| - |v|)/dt,
  * kappa = wrap(atan2(vy', vx') - yaw) / (|v| dt + a dt^2/2), kappa = 0 when

@@ -264,9 +264,11 @@ int wm_profile_collect(int which, float *total_ms, int32_t *launches)
     return rc == WM_OK ? ok() : rc;
 }
 
-int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
-            const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
-            void *stream)
+// `prepared`: the workspace already holds this road graph's compacted edges
+// (wm_roadgraph_prepare), so the compaction is skipped.
+static int step_impl(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+                     const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
+                     void *stream, bool prepared)
 {
     CHECK(check_batch(batch));
     CHECK(check_state(cur, "cur"));
@@ -301,14 +303,41 @@ int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, co
         tn.CW = 1;
         if (tn.G > 16)
             tn.G = 16;
-        wm::launch_compact_edges(*batch, *rg, w, L, st);
+        if (!prepared)
+            wm::launch_compact_edges(*batch, *rg, w, L, st);
         wm::OffroadArgs o{batch->obj_off, batch->rg_off, *next, wm::ws_edges(w, L), m->offroad, m->offroad_margin,
                           nullptr, tn.G, tn.CW};
         wm::launch_offroad(*batch, o, st);
     }
     if (m && m->reward)
         wm::launch_reward(*batch, m->collision, rg ? m->offroad : nullptr, m->reward, st);
-    return device_status("wm_step");
+    return device_status(prepared ? "wm_step_prepared" : "wm_step");
+}
+
+int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+            const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
+            void *stream)
+{
+    return step_impl(batch, cur, act, log_next, rg, dt, next, m, ws, ws_bytes, stream, false);
+}
+
+int wm_step_prepared(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+                     const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    return step_impl(batch, cur, act, log_next, rg, dt, next, m, ws, ws_bytes, stream, true);
+}
+
+int wm_roadgraph_prepare(const wm_batch *batch, const wm_roadgraph *rg, void *ws, size_t ws_bytes, void *stream)
+{
+    CHECK(check_batch(batch));
+    if (!rg)
+        return fail(WM_ERR_NULL, "roadgraph is NULL");
+    CHECK(check_rg(rg));
+    const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
+    CHECK(check_ws(ws, ws_bytes, L.total));
+    wm::launch_compact_edges(*batch, *rg, (unsigned char *)ws, L, (hipStream_t)stream);
+    return device_status("wm_roadgraph_prepare");
 }
 
 int wm_inverse_action(const wm_batch *batch, const wm_state *cur, const wm_state *next, float dt, float *accel,

@@ -645,7 +645,11 @@ __global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
         load_object(L, i, A.st, o0 + i0 + i);
     __syncthreads();
     const long eb = edge_base(__builtin_amdgcn_readfirstlane(A.rg_off[s]), s);
-    const int E = __builtin_amdgcn_readfirstlane(A.E.count[s]);
+    // the count comes from the workspace: clamped to the scenario's capacity
+    // so that a stale workspace can only give wrong values, never an access
+    // outside the scenario's edge slots
+    const int E = __builtin_amdgcn_readfirstlane(
+        max(0, min(A.E.count[s], A.rg_off[s + 1] - A.rg_off[s])));
     const float qqmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.E.qqmax[s])));
     offroad_unit(L, 0, Ns, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb, E, qqmax, A.G, A.CW, C, sk, nidx);
     for (int il = threadIdx.x; il < Ns; il += blockDim.x) {
@@ -869,7 +873,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int N = __builtin_amdgcn_readfirstlane(A.obj_off[s + 1]) - o0;
         const int i0 = slice * U, Ns = min(U, N - i0);
         const long eb = A.has_rg ? edge_base(__builtin_amdgcn_readfirstlane(A.rg_off[s]), s) : 0;
-        const int E = A.has_rg ? __builtin_amdgcn_readfirstlane(A.E.count[s]) : 0;
+        const int E = A.has_rg ? __builtin_amdgcn_readfirstlane(
+                                     max(0, min(A.E.count[s], A.rg_off[s + 1] - A.rg_off[s])))
+                               : 0;
         const float qqmax = A.has_rg ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.E.qqmax[s]))) : 0.f;
         for (int i = tid; i < N; i += nthr) {
             load_object(L, i, A.init, o0 + i);

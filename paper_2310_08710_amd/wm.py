@@ -94,6 +94,8 @@ def lib() -> C.CDLL:
         L.wm_step.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
                               C.POINTER(CRoadgraph), C.c_float, C.POINTER(CState), C.POINTER(CMetrics), _P,
                               C.c_size_t, _P]
+        L.wm_step_prepared.argtypes = L.wm_step.argtypes
+        L.wm_roadgraph_prepare.argtypes = [C.POINTER(CBatch), C.POINTER(CRoadgraph), _P, C.c_size_t, _P]
         L.wm_inverse_action.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CState), C.c_float, _P, _P,
                                         _P, _P]
         L.wm_overlap.argtypes = [C.POINTER(CBatch), C.POINTER(CState), _P, _P, _P, _P, _P, _P]
@@ -281,14 +283,29 @@ def _tune(t):
 # ---------------------------------------------------------------------------
 # Entry points (same names as the C ABI)
 # ---------------------------------------------------------------------------
-def step(batch: Batch, cur: State, act: Action, log_next: State, rg: Optional[Roadgraph], dt: float, nxt: State,
-         metrics: Optional[Metrics] = None, ws: Optional[torch.Tensor] = None, stream=None):
+def _step(fn, batch, cur, act, log_next, rg, dt, nxt, metrics, ws, stream):
     b, c, a, l, n = batch.c(), cur.c(), act.c(), log_next.c(), nxt.c()
     r = rg.c() if rg is not None else None
     m = metrics.c() if metrics is not None else None
-    _check(lib().wm_step(C.byref(b), C.byref(c), C.byref(a), C.byref(l), C.byref(r) if r is not None else None,
-                         dt, C.byref(n), C.byref(m) if m is not None else None, _ptr(ws),
-                         ws.numel() if ws is not None else 0, _stream(stream)))
+    _check(fn(C.byref(b), C.byref(c), C.byref(a), C.byref(l), C.byref(r) if r is not None else None, dt, C.byref(n),
+              C.byref(m) if m is not None else None, _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream)))
+
+
+def step(batch: Batch, cur: State, act: Action, log_next: State, rg: Optional[Roadgraph], dt: float, nxt: State,
+         metrics: Optional[Metrics] = None, ws: Optional[torch.Tensor] = None, stream=None):
+    _step(lib().wm_step, batch, cur, act, log_next, rg, dt, nxt, metrics, ws, stream)
+
+
+def roadgraph_prepare(batch: Batch, rg: Roadgraph, ws: torch.Tensor, stream=None):
+    """Compact the road edges into `ws` once for step_prepared()."""
+    b, r = batch.c(), rg.c()
+    _check(lib().wm_roadgraph_prepare(C.byref(b), C.byref(r), ws.data_ptr(), ws.numel(), _stream(stream)))
+
+
+def step_prepared(batch: Batch, cur: State, act: Action, log_next: State, rg: Optional[Roadgraph], dt: float,
+                  nxt: State, metrics: Optional[Metrics], ws: torch.Tensor, stream=None):
+    """step() reusing the edges that roadgraph_prepare() compacted into `ws`."""
+    _step(lib().wm_step_prepared, batch, cur, act, log_next, rg, dt, nxt, metrics, ws, stream)
 
 
 def inverse_action(batch: Batch, cur: State, nxt: State, dt: float, accel: torch.Tensor, curvature: torch.Tensor,

@@ -267,3 +267,29 @@ def test_observe_every_step_of_a_sequence():
         wm.observe(ds.batch, traj.row(t), ds.rg, ds.ego, E, k, one, None, of1)
         torch.cuda.synchronize()
         assert torch.equal(one, idx2[t]) and torch.equal(of1, of2[t]), t
+
+
+def test_prepared_steps_equal_plain_steps():
+    """wm_step_prepared after one wm_roadgraph_prepare gives the same states
+    and metrics as wm_step, which compacts the road edges at every call."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _ragged(T=8)
+    ds = wm.upload(sc, dev)
+    traj, met = _run_plain(ds, sc, dev)
+    n, T = sc.total_objects, sc.steps
+    t2 = wm.State.empty((T, n), dev)
+    m2 = wm.Metrics.empty((T, n), dev)
+    ws = ds.batch.workspace()
+    wm.roadgraph_prepare(ds.batch, ds.rg, ws)
+    cur = ds.init
+    for t in range(1, T + 1):
+        act = wm.Action(ds.act_seq.accel[t - 1], ds.act_seq.curvature[t - 1], ds.act_seq.controlled)
+        wm.step_prepared(ds.batch, cur, act, ds.log_seq.row(t), ds.rg, sc.dt, t2.row(t - 1), m2.row(t - 1), ws)
+        cur = t2.row(t - 1)
+    torch.cuda.synchronize()
+    for f in synth.STATE_FIELDS + ("valid",):
+        assert torch.equal(getattr(traj, f), getattr(t2, f)), f
+    for f in wm.Metrics.FIELDS:
+        assert torch.equal(getattr(met, f), getattr(m2, f)), f
