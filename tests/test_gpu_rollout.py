@@ -293,3 +293,29 @@ def test_prepared_steps_equal_plain_steps():
         assert torch.equal(getattr(traj, f), getattr(t2, f)), f
     for f in wm.Metrics.FIELDS:
         assert torch.equal(getattr(met, f), getattr(m2, f)), f
+
+
+def test_largest_scenario_fused_equals_plain_and_oracle():
+    """Scenarios with the largest supported object count (1024): the fused
+    rollout (units of 64 objects, all 1024 partners in LDS) equals the plain
+    steps and matches the oracle."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = synth.make_scene(2, scenarios=2, objects=(1024, 1024), rg_points=(2000, 2400), steps=3, object_box=100,
+                          invalid_frac=0.05, on_road_frac=0.3)
+    assert int(np.diff(sc.obj_off).max()) == 1024
+    ds = wm.upload(sc, dev)
+    traj, met, loss, _ = _run_fused(ds, sc, dev)
+    ptraj, pmet = _run_plain(ds, sc, dev)
+    for f in synth.STATE_FIELDS + ("valid",):
+        assert torch.equal(getattr(traj, f), getattr(ptraj, f)), f
+    for f in wm.Metrics.FIELDS:
+        assert torch.equal(getattr(met, f), getattr(pmet, f)), f
+    T = sc.steps
+    lw = sc.log_window()
+    init = f64({k: v[0] for k, v in lw.items()})
+    ref = oracle.rollout(sc.obj_off, sc.rg_off, init, sc.accel, sc.curvature, sc.controlled, f64(lw), f64(sc.rg), T,
+                         sc.dt)
+    gm = {f: getattr(met, f).cpu().numpy() for f in METRICS}
+    compare_rollout(traj.numpy(), gm, loss.cpu().numpy(), ref, sc.obj_off, sc.rg_off, f64(sc.rg))
