@@ -4,12 +4,16 @@
  * The library implements the batched simulator step of "Waymax: An
  * Accelerated, Data-Driven Simulator for Large-Scale Autonomous Driving
  * Research" (arXiv 2310.08710) with hand-written HIP kernels:
- *   - kinematic bicycle dynamics, forward and inverse (App. A.1),
+ *   - kinematic bicycle dynamics, forward and inverse, and the delta action
+ *     space (App. A.1); discretized actions (Sec. 5.2),
  *   - the per-step metrics of Sec. 3.4: collision (box overlap), off-road
- *     (side of the nearest oriented road edge) and displacement error,
+ *     (side of the nearest oriented road edge), displacement error and
+ *     kinematic infeasibility, plus the sparse reward of Sec. 5.2,
  *   - the default observation of Sec. 3.2 (ego frame + k nearest road points),
- *   - fused multi-step rollouts (Sec. 5.1, Rollout) and their adjoint
- *     (differentiable simulation, Sec. 1 and Sec. 6).
+ *     for one state or every step of a state sequence,
+ *   - fused multi-step rollouts (Sec. 5.1, Rollout), with log playback or IDM
+ *     sim agents (Sec. 3.5), and their adjoint (differentiable simulation,
+ *     Sec. 1 and Sec. 6).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -22,7 +26,8 @@
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
  *    the call returns without synchronizing.  Calls contain no host-device
  *    synchronization, no allocation and no memset, so a sequence of them can
- *    be captured into a HIP graph.
+ *    be captured into a HIP graph (wm_autotune, which times launches, is the
+ *    exception).
  *  - Batches are packed (CSR): scenario s owns objects obj_off[s] ..
  *    obj_off[s+1]-1 and road points rg_off[s] .. rg_off[s+1]-1 of the global
  *    arrays.  Objects of different scenarios never interact.

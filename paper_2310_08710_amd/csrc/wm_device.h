@@ -20,10 +20,6 @@ constexpr int kChunk = kEdgeChunk;    // road-edge points per chunk of the off-r
 constexpr float kNoValue = -FLT_MAX;  // margin with no defined value
 constexpr float kSoftScale = 0.1f;    // soft-overlap scale of the training loss [m]
 
-// Pointer into the constant address space: loads through it whose address is
-// wave-uniform become scalar (SMEM) loads that feed VALU ops as SGPR operands.
-typedef const float __attribute__((address_space(4))) *uniform_fptr;
-
 // Scenario-major packed state kept in LDS by the fused kernels.
 struct ObjLds {
     float *x, *y, *yaw, *vx, *vy, *len, *wid, *c, *s;
@@ -226,8 +222,8 @@ __device__ __forceinline__ float edge_d2(float qx, float qy, float cx, float cy)
 // ---------------------------------------------------------------------------
 // Off-road scan (the hot loop).  A wave scans chunks [c0, c1) of one
 // scenario's compacted road-edge stream (Edges) against R corners held per
-// lane.  The edge address is wave-uniform, so every point arrives once per
-// wave by a scalar load and is an SGPR operand for all 64 lanes.
+// lane.  Each chunk passes once through the wave's LDS stage and reaches all
+// 64 lanes as broadcast reads.
 //
 // The inner loop evaluates the expanded form
 //     T(q) = |q|^2 - 2 c.q  ( = |q - c|^2 - |c|^2 )
@@ -239,9 +235,9 @@ __device__ __forceinline__ float edge_d2(float qx, float qy, float cx, float cy)
 // chunk whose T-minimum exceeds the best one by more than
 //     delta = 2^-19 (Rq + |c|)^2      (Rq = max |q| of the scenario)
 // cannot hold a point whose D is the minimum.  The candidate chunks (one or
-// two; otherwise the whole list) are then rescanned with D, and the lowest
-// index of the minimum of D is the nearest point -- the same result as an
-// exact scan of D over all points.
+// two; with three or more, every point) are then rescanned with D, and the
+// lowest index of the minimum of D is the nearest point -- the same result as
+// an exact scan of D over all points.
 // ---------------------------------------------------------------------------
 constexpr int kChunkFloats = 3 * kChunk;
 

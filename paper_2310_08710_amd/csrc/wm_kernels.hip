@@ -862,8 +862,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (tid == 0)
             s_unit = atomicAdd(A.counter, 1);
         __syncthreads();
-        // every value that selects road-edge addresses is made provably
-        // wave-uniform, so the scan's edge loads become scalar loads
+        // the unit, its scenario and the scan's chunk ranges are made provably
+        // wave-uniform (scalar registers)
         const int q = __builtin_amdgcn_readfirstlane(s_unit);
         if (q >= __builtin_amdgcn_readfirstlane(A.counter[1]))
             break;
