@@ -210,12 +210,13 @@ def test_offroad_exact_ties_and_empty_scenarios():
 
 
 @pytest.mark.parametrize("tune", [(64, 1), (64, 2), (64, 8)])
-@pytest.mark.parametrize("positions", [(10, 70), (10, 70, 130, 200), (63, 64), (5, 6, 7, 300)])
+@pytest.mark.parametrize("positions", [(10, 200), (10, 160, 230, 300), (149, 150), (5, 6, 7, 300)])
 def test_offroad_candidate_chunks(tune, positions):
     """Exact distance ties between road-edge points that fall into different
-    64-point chunks of the scan: the scan's expanded distance cannot separate
-    them, so one-, two- and many-chunk rescans must all return the lowest
-    index, as the oracle does."""
+    128-point chunks of the scan (compacted indices 8 | 171; 8 | 137, 197 |
+    257; 127 | 128; 4, 5, 6 | 258): the scan's expanded distance cannot
+    separate them, so one-, two- and three-chunk (exact scan of every point)
+    cases must all return the lowest index, as the oracle does."""
     import torch
     from paper_2310_08710_amd import wm
     dev = device()
