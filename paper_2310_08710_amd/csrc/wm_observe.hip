@@ -2,13 +2,26 @@
 // and the k road points nearest to the ego, exact, ascending by
 // (binary32 squared distance, index).
 //
-// One 1024-thread work-group per (scenario, ego) and state row.  Each thread keeps up to 32
-// keys in registers (points j = tid + 1024 r), so a scenario's road graph is
-// read once per ego.  The k-th smallest key is found by a 3-pass radix select
-// (11 + 11 + 10 bits of the float bits, which order like the values because
-// the keys are non-negative) with LDS histograms; the points with a smaller
-// key plus the lowest-index points equal to it are compacted and sorted by a
-// bitonic network on (key << 32 | index).
+// One 1024-thread work-group per (row, scenario, ego).  Each thread keeps up
+// to 32 keys in registers (points j = tid + 1024 r), so a scenario's road
+// graph is read once per ego.  The keys are non-negative floats, whose bit
+// patterns order like their values.
+//   1. Every 16th point is sampled; a histogram of the samples' first digit
+//      (key bits 20..30: exponent and three mantissa bits) gives a bound U
+//      below which about 1.5 k keys should lie.  The keys below U are counted
+//      exactly; if there are at least k of them (and no more than an LDS list
+//      holds), they are compacted into that list and the rest are never
+//      touched again.  Otherwise every key stays a candidate.
+//   2. A first-digit histogram of the candidates locates the bin b holding
+//      the k-th key; every candidate below that bin is selected.
+//   3. The keys of bin b (rarely more than a few hundred; otherwise further
+//      10-bit digits narrow it first) are ranked among themselves by
+//      (key, index), and the lowest ones fill the last places.
+//   4. The selected keys below bin b are scattered into LDS grouped by their
+//      bin, whose output range is known from the histogram's prefix sum, and
+//      each one's place is the start of its bin plus the number of keys of
+//      that bin that precede it.
+// No sorting network: about fourteen work-group barriers per ego.
 #include "wm_device.h"
 #include "wm_internal.h"
 
@@ -16,34 +29,39 @@ namespace wm {
 
 constexpr int kObsThreads = 1024;
 constexpr int kObsKeys = WM_MAX_OBSERVE_POINTS / kObsThreads;  // 32
-constexpr uint32_t kNoKey = 0xffffffffu;                        // invalid point / padding
-constexpr int kHistBins = 2048;                                 // widest radix digit: 11 bits
+constexpr uint32_t kNoKey = 0xffffffffu;                        // invalid point
+constexpr uint32_t kAllKeys = 0x80000000u;                      // above every valid key
+constexpr int kBins = 2048;                                     // first digit: key bits 20..30
+constexpr int kDigitShift = 20;
 constexpr int kHistCopies = 4;
+constexpr int kCandCap = 1024;                                  // boundary keys ranked directly
+constexpr int kListCap = 4096;                                  // candidates compacted into LDS
+constexpr int kSampleMask = 15;                                 // points j with j % 16 == 0 are sampled
 
 __device__ __forceinline__ uint32_t topk_key(float qx, float qy, float ex, float ey)
 {
     const float dx = qx - ex, dy = qy - ey;
     const float xx = dx * dx, yy = dy * dy;  // no contraction: fl(fl(dx*dx) + fl(dy*dy))
-    return __float_as_uint(xx + yy);
+    return __float_as_uint(xx + yy) & 0x7fffffffu;
 }
 
-// Block-wide exclusive prefix of a per-thread count (wave ballot-free: small
-// values); returns the exclusive prefix and writes the block total to *total.
-__device__ __forceinline__ int block_exclusive(int v, int *wtot, int *total)
+// Block-wide exclusive prefix of a per-thread count; returns the exclusive
+// prefix and writes the block total to *total.  Two barriers.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *wtot, uint32_t *total)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int incl = v;
+    uint32_t incl = v;
     for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(incl, d);
+        const uint32_t u = __shfl_up(incl, d);
         if (lane >= d)
             incl += u;
     }
     if (lane == 63)
         wtot[w] = incl;
     __syncthreads();
-    int off = 0, tot = 0;
+    uint32_t off = 0, tot = 0;
     for (int i = 0; i < kObsThreads / 64; ++i) {
-        off += (i < w) ? wtot[i] : 0;
+        off += (i < w) ? wtot[i] : 0u;
         tot += wtot[i];
     }
     __syncthreads();
@@ -51,55 +69,284 @@ __device__ __forceinline__ int block_exclusive(int v, int *wtot, int *total)
     return off + incl - v;
 }
 
-__global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A0)
+// Number of entries of a[lo, hi) below `own`, four loads in flight.
+__device__ __forceinline__ int count_below(const uint64_t *a, int lo, int hi, uint64_t own)
 {
-    // grid y: the state row (time step) observed, with its own outputs
-    ObserveArgs A = A0;
-    if (blockIdx.y > 0) {
-        const long t = blockIdx.y, so = t * A0.n, slots = A0.S * A0.E;
-        A.st.x += so;
-        A.st.y += so;
-        A.st.yaw += so;
-        A.st.vx += so;
-        A.st.vy += so;
-        A.st.length += so;
-        A.st.width += so;
-        A.st.valid += so;
-        A.rg_idx += t * slots * A0.k;
-        if (A.rg_feat)
-            A.rg_feat += t * slots * A0.k * 4;
-        if (A.obj_feat)
-            A.obj_feat += t * slots * A0.maxN * 8;
+    int c = 0, q = lo;
+    for (; q + 4 <= hi; q += 4) {
+        const uint64_t a0 = a[q], a1 = a[q + 1], a2 = a[q + 2], a3 = a[q + 3];
+        c += (int)(a0 < own) + (int)(a1 < own) + (int)(a2 < own) + (int)(a3 < own);
     }
-    // four copies of the radix histogram, lane l counting into copy l % 4,
-    // so that lanes of one wave with equal digits do not all hit one address
-    __shared__ int hist[kHistCopies * kHistBins];
-    __shared__ int wtot[kObsThreads / 64];
-    __shared__ uint64_t sel[1024];
-    __shared__ int sh_bin, sh_before, sh_count;
+    for (; q < hi; ++q)
+        c += a[q] < own;
+    return c;
+}
+
+struct ObsOut {
+    int32_t *idx;
+    float *feat;
+    const float *x, *y, *dx, *dy;
+    float ex, ey, es, ec;
+};
+
+// Output place `pos` of this ego receives the scenario's road point `j`
+// (h: its position in the packed arrays).
+__device__ __forceinline__ void emit(const ObsOut &o, long pos, int j, int h)
+{
+    o.idx[pos] = j;
+    if (o.feat) {
+        const float dx = o.x[h] - o.ex, dy = o.y[h] - o.ey;
+        float *f = o.feat + 4 * pos;
+        f[0] = __builtin_fmaf(o.ec, dx, o.es * dy);
+        f[1] = __builtin_fmaf(o.ec, dy, -(o.es * dx));
+        f[2] = __builtin_fmaf(o.ec, o.dx[h], o.es * o.dy[h]);
+        f[3] = __builtin_fmaf(o.ec, o.dy[h], -(o.es * o.dx[h]));
+    }
+}
+
+struct TopkLds {
+    int *hist;           // [kHistCopies][kBins] digit histograms; copy 0 then the scatter cursors
+    int *base;           // [kBins + 1] exclusive prefix of the first-digit histogram
+    uint64_t *sel;       // [WM_MAX_TOPK] selected keys below the boundary, grouped by bin
+    uint64_t *cand;      // [kCandCap] keys of the boundary set
+    uint32_t *wtot;      // [16] per-wave totals of block_exclusive
+    int *sh;             // [4] bin, before, count, boundary-list length
+};
+
+// Candidates held in registers: point j = tid + 1024 r has key[r].
+struct RegKeys {
+    const uint32_t *key;
+    template <class F> __device__ __forceinline__ void each(F &&f) const
+    {
+#pragma unroll
+        for (int r = 0; r < kObsKeys; ++r)
+            f(key[r], (int)threadIdx.x + kObsThreads * r, r);
+    }
+};
+
+// Candidates compacted into LDS as (key << 32 | j).
+struct ListKeys {
+    const uint64_t *list;
+    int n;
+    template <class F> __device__ __forceinline__ void each(F &&f) const
+    {
+        for (int i = threadIdx.x; i < n; i += kObsThreads) {
+            const uint64_t e = list[i];
+            f((uint32_t)(e >> 32), (int)(uint32_t)e, 0);
+        }
+    }
+};
+
+// Selects and writes the kk (>= 1, <= number of candidates) smallest
+// candidates in (key, index) order; every candidate not given is larger than
+// every one given.  Returns false, having written nothing, when the boundary
+// set is over kCandCap equal keys and the candidates are not the registers
+// (whose fixed index order that case needs).  Work-group-wide; every thread
+// calls it with the same arguments.
+template <bool kReg, class Src>
+__device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLds &L, const ObsOut &o, int p0)
+{
     const int tid = threadIdx.x;
-    const int slot = blockIdx.x;                 // s * E + e
-    const int s = slot / A.E;
+    __syncthreads();   // earlier readers of the LDS arrays are done
+    for (int b = tid; b < kHistCopies * kBins; b += kObsThreads)
+        L.hist[b] = 0;
+    if (tid < 4)
+        L.sh[tid] = 0;
+    __syncthreads();
+
+    // ---- first digit: histogram, prefix, the bin holding the kk-th key ----
+    int *myhist = L.hist + kBins * (tid & (kHistCopies - 1));
+    src.each([&](uint32_t k, int, int) {
+        if (k != kNoKey)
+            atomicAdd(&myhist[k >> kDigitShift], 1);
+    });
+    __syncthreads();
+    int c0 = 0, c1 = 0;   // bins 2 tid and 2 tid + 1, copies summed
+    for (int c = 0; c < kHistCopies; ++c) {
+        c0 += L.hist[kBins * c + 2 * tid];
+        c1 += L.hist[kBins * c + 2 * tid + 1];
+    }
+    uint32_t tot;
+    const int ex0 = (int)block_exclusive((uint32_t)(c0 + c1), L.wtot, &tot);
+    L.base[2 * tid] = ex0;
+    L.base[2 * tid + 1] = ex0 + c0;
+    if (tid == 0)
+        L.base[kBins] = (int)tot;
+    // only this thread read its two bins: they become its scatter cursors
+    L.hist[2 * tid] = ex0;
+    L.hist[2 * tid + 1] = ex0 + c0;
+    if (ex0 <= kk - 1 && kk - 1 < ex0 + c0 + c1) {
+        const bool first = kk - 1 < ex0 + c0;
+        L.sh[0] = 2 * tid + (first ? 0 : 1);
+        L.sh[1] = first ? ex0 : ex0 + c0;
+        L.sh[2] = first ? c0 : c1;
+    }
+    __syncthreads();
+    // block-uniform from here on (read into scalar registers)
+    const int b1 = __builtin_amdgcn_readfirstlane(L.sh[0]);
+    uint32_t prefix = (uint32_t)b1 << kDigitShift, pmask = ~0u << kDigitShift;
+    int c_less = __builtin_amdgcn_readfirstlane(L.sh[1]);   // candidates below the boundary set: all selected
+    int nB = __builtin_amdgcn_readfirstlane(L.sh[2]);       // candidates with (key & pmask) == prefix
+
+    // ---- a boundary bin too large to rank directly: narrow it by the
+    // next 10-bit digits ----
+    if (nB > kCandCap) {
+        for (int sh = 10; sh >= 0 && nB > kCandCap; sh -= 10) {
+            __syncthreads();
+            for (int c = 0; c < kHistCopies; ++c)
+                L.hist[kBins * c + tid] = 0;
+            __syncthreads();
+            src.each([&](uint32_t k, int, int) {
+                if ((k & pmask) == prefix)   // never true for kNoKey: prefix < 2^31
+                    atomicAdd(&myhist[(k >> sh) & 1023], 1);
+            });
+            __syncthreads();
+            int cnt = 0;
+            for (int c = 0; c < kHistCopies; ++c)
+                cnt += L.hist[kBins * c + tid];
+            uint32_t t2;
+            const int exb = (int)block_exclusive((uint32_t)cnt, L.wtot, &t2);
+            const int rank = kk - 1 - c_less;
+            if (rank >= exb && rank < exb + cnt) {
+                L.sh[0] = tid;
+                L.sh[1] = exb;
+                L.sh[2] = cnt;
+            }
+            __syncthreads();
+            prefix |= (uint32_t)__builtin_amdgcn_readfirstlane(L.sh[0]) << sh;
+            pmask |= 1023u << sh;
+            c_less += __builtin_amdgcn_readfirstlane(L.sh[1]);
+            nB = __builtin_amdgcn_readfirstlane(L.sh[2]);
+        }
+        if (!kReg && nB > kCandCap)
+            return false;
+        __syncthreads();
+        L.hist[2 * tid] = L.base[2 * tid];
+        L.hist[2 * tid + 1] = L.base[2 * tid + 1];
+        if (tid == 0)
+            L.sh[3] = 0;
+        __syncthreads();
+    }
+    const int need = kk - c_less;   // places taken from the boundary set
+
+    // ---- scatter the candidates below the boundary; collect the boundary
+    // set (or, when it is too large, mark its members: bit r of eqm) ----
+    const bool direct = nB <= kCandCap;
+    uint32_t eqm = 0;
+    src.each([&](uint32_t k, int j, int r) {
+        // kNoKey is neither below prefix nor in the boundary set
+        const uint64_t ent = ((uint64_t)k << 32) | (uint32_t)j;
+        if (k < prefix)
+            L.sel[atomicAdd(&L.hist[k >> kDigitShift], 1)] = ent;
+        else if ((k & pmask) == prefix) {
+            if (!kReg || direct)
+                L.cand[atomicAdd(&L.sh[3], 1)] = ent;
+            else
+                eqm |= 1u << r;
+        }
+    });
+    __syncthreads();
+
+    // ---- the boundary set: rank among itself, keep the lowest `need` ----
+    if (direct) {
+        for (int c = tid; c < nB; c += kObsThreads) {
+            const uint64_t own = L.cand[c];
+            const int before = count_below(L.cand, 0, nB, own);
+            if (before < need) {
+                const int j = (int)(uint32_t)own;
+                emit(o, c_less + before, j, p0 + j);
+            }
+        }
+    } else if (kReg) {
+        // every key of the boundary set is equal (all digits fixed): the
+        // lowest indices win.  Index order is j = tid + 1024 r: round r
+        // first, then wave, then lane; wave counts per round go through LDS.
+        const int lane = tid & 63, wv = tid >> 6;
+        int *wc = L.hist + kBins;   // [round][wave]; this histogram copy is no longer needed
+        for (int r = 0; r < kObsKeys; ++r) {
+            const int cnt = __popcll(__ballot((eqm >> r) & 1u));
+            if (lane == 0)
+                wc[r * (kObsThreads / 64) + wv] = cnt;
+        }
+        __syncthreads();
+        int rounds_before = 0;
+        for (int r = 0; r < kObsKeys; ++r) {
+            const uint64_t bal = __ballot((eqm >> r) & 1u);
+            int waves_before = 0, round_tot = 0;
+            for (int v = 0; v < kObsThreads / 64; ++v) {
+                const int c = wc[r * (kObsThreads / 64) + v];
+                round_tot += c;
+                waves_before += v < wv ? c : 0;
+            }
+            if ((eqm >> r) & 1u) {
+                const int rk = rounds_before + waves_before + __popcll(bal & ((1ull << lane) - 1ull));
+                if (rk < need) {
+                    const int j = tid + kObsThreads * r;
+                    emit(o, c_less + rk, j, p0 + j);
+                }
+            }
+            rounds_before += round_tot;
+        }
+    }
+    // ---- candidates below the boundary: start of the bin + rank inside it ----
+    for (int i = tid; i < c_less; i += kObsThreads) {
+        const uint64_t own = L.sel[i];
+        const int d = (int)(own >> (32 + kDigitShift));
+        const int start = L.base[d], end = d == b1 ? c_less : L.base[d + 1];
+        const int j = (int)(uint32_t)own;
+        emit(o, start + count_below(L.sel, start, end, own), j, p0 + j);
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A, int rows)
+{
+    // Work item w = (s * rows + row) * E + e.  Work-groups are dispatched to
+    // the eight XCDs in turn; each XCD takes a contiguous range of w, so the
+    // egos and rows of one scenario share that XCD's L2 copy of its road graph.
+    const long W = (long)rows * A.S * A.E;
+    const long p = blockIdx.x, full = W / 8 * 8;
+    const long w = p < full ? (p % 8) * (W / 8) + p / 8 : p;
+    const int e = (int)(w % A.E);
+    const long sr = w / A.E;
+    const int row = (int)(sr % rows), s = (int)(sr / rows);
+    const int slot = s * A.E + e;
+    const long so = (long)row * A.n, orow = (long)row * A.S * A.E;
+
+    __shared__ int hist[kHistCopies * kBins];
+    __shared__ int base[kBins + 1];
+    __shared__ uint64_t sel[WM_MAX_TOPK];
+    __shared__ uint64_t cand[kCandCap];
+    __shared__ uint64_t list[kListCap];
+    __shared__ int hs[kBins];                   // first-digit histogram of the sampled keys
+    __shared__ uint32_t wtot[kObsThreads / 64];
+    __shared__ int sh[4];
+    __shared__ uint32_t sh_bound;
+    const TopkLds L{hist, base, sel, cand, wtot, sh};
+    const int tid = threadIdx.x;
     const int o0 = A.obj_off[s], N = A.obj_off[s + 1] - o0;
     const int p0 = A.rg_off[s], P = A.rg_off[s + 1] - p0;
     const int g = A.ego[slot];
-    const long out0 = (long)slot * A.k;
-    const bool ego_valid = A.st.valid[g];
-    const float ex = A.st.x[g], ey = A.st.y[g];
+    const bool ego_valid = A.st.valid[so + g];
+    const float ex = A.st.x[so + g], ey = A.st.y[so + g], eyaw = A.st.yaw[so + g];
     float es, ec;
-    sincosf(A.st.yaw[g], &es, &ec);
+    sincosf(eyaw, &es, &ec);
+    for (int b = tid; b < kBins; b += kObsThreads)
+        hs[b] = 0;
+    if (tid == 0)
+        sh_bound = kAllKeys;
 
     // ---- objects in the ego frame ----
     if (A.obj_feat) {
-        float *of = A.obj_feat + (long)slot * A.maxN * 8;
+        float *of = A.obj_feat + (orow + slot) * A.maxN * 8;
         for (int j = tid; j < A.maxN; j += kObsThreads) {
             float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (ego_valid && j < N && A.st.valid[o0 + j]) {
-                const int h = o0 + j;
+            const long h = so + o0 + j;
+            if (ego_valid && j < N && A.st.valid[h]) {
                 const float dx = A.st.x[h] - ex, dy = A.st.y[h] - ey;
                 f[0] = __builtin_fmaf(ec, dx, es * dy);
                 f[1] = __builtin_fmaf(ec, dy, -(es * dx));
-                f[2] = wrap_angle(A.st.yaw[h] - A.st.yaw[g]);
+                f[2] = wrap_angle(A.st.yaw[h] - eyaw);
                 f[3] = __builtin_fmaf(ec, A.st.vx[h], es * A.st.vy[h]);
                 f[4] = __builtin_fmaf(ec, A.st.vy[h], -(es * A.st.vx[h]));
                 f[5] = A.st.length[h];
@@ -113,155 +360,86 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A0)
 
     // ---- keys ----
     uint32_t key[kObsKeys];
-    int nvalid_local = 0;
 #pragma unroll
-    for (int r = 0; r < kObsKeys; ++r) {
-        const int j = tid + kObsThreads * r;
-        uint32_t kk = kNoKey;
-        if (ego_valid && j < P && A.rg.valid[p0 + j])
-            kk = topk_key(A.rg.x[p0 + j], A.rg.y[p0 + j], ex, ey);
-        key[r] = kk;
-        nvalid_local += kk != kNoKey;
-    }
-    int nvalid;
-    (void)block_exclusive(nvalid_local, wtot, &nvalid);
-    const int kk = min(A.k, nvalid);
-
-    // ---- radix select of the kk-th smallest key (rank kk-1) ----
-    uint32_t prefix = 0, pmask = 0;
-    int rank = kk - 1;
-    const int shifts[3] = {21, 10, 0};
-    const int widths[3] = {11, 11, 10};
-    int *myhist = hist + kHistBins * (tid & (kHistCopies - 1));
-    for (int pass = 0; pass < 3 && kk > 0; ++pass) {
-        const int sh = shifts[pass], nb = 1 << widths[pass];
-        for (int b = tid; b < kHistCopies * kHistBins; b += kObsThreads)
-            hist[b] = 0;
-        __syncthreads();
+    for (int r = 0; r < kObsKeys; ++r)
+        key[r] = kNoKey;
+    if (ego_valid && P > 0) {
+        // indices past the scenario's points are clamped to its last point
+        // (an in-bounds load) and give no key
+        const float *rx = A.rg.x + p0, *ry = A.rg.y + p0;
+        const uint8_t *rv = A.rg.valid + p0;
 #pragma unroll
-        for (int r = 0; r < kObsKeys; ++r)
-            if (key[r] != kNoKey && (key[r] & pmask) == prefix)
-                atomicAdd(&myhist[(key[r] >> sh) & (nb - 1)], 1);
-        __syncthreads();
-        // find the bin holding `rank`: per-thread bin groups (copies summed),
-        // then a block scan
-        const int per = nb / kObsThreads > 0 ? nb / kObsThreads : 1;
-        const int b0 = tid * per;
-        int cnt = 0;
-        if (b0 < nb)
-            for (int b = b0; b < b0 + per; ++b)
-                for (int c = 0; c < kHistCopies; ++c)
-                    cnt += hist[kHistBins * c + b];
-        int total;
-        int before = block_exclusive(b0 < nb ? cnt : 0, wtot, &total);
-        if (b0 < nb && rank >= before && rank < before + cnt) {
-            int acc = before;
-            for (int b = b0; b < b0 + per; ++b) {
-                int hb = 0;
-                for (int c = 0; c < kHistCopies; ++c)
-                    hb += hist[kHistBins * c + b];
-                if (rank < acc + hb) {
-                    sh_bin = b;
-                    sh_before = acc;
-                    break;
-                }
-                acc += hb;
-            }
-        }
-        __syncthreads();
-        prefix |= (uint32_t)sh_bin << sh;
-        pmask |= (uint32_t)(nb - 1) << sh;
-        rank -= sh_before;
-        __syncthreads();
-    }
-    const uint32_t kth = prefix;   // the kk-th smallest key (when kk > 0)
-
-    // ---- compaction: keys < kth, then the lowest-index keys == kth ----
-    int nless_local = 0, nle_local = 0;
-#pragma unroll
-    for (int r = 0; r < kObsKeys; ++r) {
-        nless_local += (kk > 0 && key[r] < kth);
-        nle_local += (kk > 0 && key[r] <= kth);
-    }
-    int nless, nle;
-    (void)block_exclusive(nless_local, wtot, &nless);
-    const int le_before = block_exclusive(nle_local, wtot, &nle);
-    const int need_eq = kk - nless;
-    if (nle == kk) {
-        // no tie to break at the k-th key: every key <= kth is selected; each
-        // thread writes its keys at its exclusive prefix (order is irrelevant:
-        // the list is sorted below)
-        int pos = le_before;
-#pragma unroll
-        for (int r = 0; r < kObsKeys; ++r)
-            if (kk > 0 && key[r] <= kth)
-                sel[pos++] = ((uint64_t)key[r] << 32) | (uint32_t)(tid + kObsThreads * r);
-    } else {
-        // more keys equal the k-th than are needed: the lowest indices win,
-        // ranked in index order (j = tid + 1024 r) one round r at a time
-        if (tid == 0)
-            sh_count = 0;
-        __syncthreads();
-        int eq_seen = 0;   // equal keys at lower index, summed over earlier rounds
         for (int r = 0; r < kObsKeys; ++r) {
-            const bool eq = kk > 0 && key[r] == kth;
-            int tot;
-            const int ex_rank = block_exclusive(eq ? 1 : 0, wtot, &tot);
-            const bool take = (kk > 0 && key[r] < kth) || (eq && eq_seen + ex_rank < need_eq);
-            if (take) {
-                const int pos = atomicAdd(&sh_count, 1);
-                sel[pos] = ((uint64_t)key[r] << 32) | (uint32_t)(tid + kObsThreads * r);
-            }
-            eq_seen += tot;
+            const int j = tid + kObsThreads * r, jj = min(j, P - 1);
+            const float qx = rx[jj], qy = ry[jj];
+            const bool v = rv[jj] != 0;
+            const uint32_t kq = topk_key(qx, qy, ex, ey);
+            key[r] = (j < P && v) ? kq : kNoKey;
         }
     }
-    __syncthreads();
-    // pad to a power of two and sort ascending
-    int m = 1;
-    while (m < kk)
-        m <<= 1;
-    for (int i = kk + tid; i < m; i += kObsThreads)
-        sel[i] = ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= m; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < m; i += kObsThreads) {
-                const int partner = i ^ stride;
-                if (partner > i) {
-                    const bool up = (i & size) == 0;
-                    const uint64_t a = sel[i], b = sel[partner];
-                    if ((a > b) == up) {
-                        sel[i] = b;
-                        sel[partner] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    __syncthreads();   // hs cleared
+
+    // ---- sample: valid count and the bound U ----
+    int nv_local = 0;
+#pragma unroll
+    for (int r = 0; r < kObsKeys; ++r) {
+        nv_local += key[r] != kNoKey;
+        if ((tid & kSampleMask) == 0 && key[r] != kNoKey)
+            atomicAdd(&hs[key[r] >> kDigitShift], 1);
     }
-    // ---- outputs ----
-    for (int r = tid; r < A.k; r += kObsThreads) {
-        int idx = -1;
-        float f[4] = {0.f, 0.f, 0.f, 0.f};
-        if (r < kk) {
-            idx = (int)(uint32_t)(sel[r] & 0xffffffffu);
-            const int h = p0 + idx;
-            const float dx = A.rg.x[h] - ex, dy = A.rg.y[h] - ey;
-            f[0] = __builtin_fmaf(ec, dx, es * dy);
-            f[1] = __builtin_fmaf(ec, dy, -(es * dx));
-            f[2] = __builtin_fmaf(ec, A.rg.dir_x[h], es * A.rg.dir_y[h]);
-            f[3] = __builtin_fmaf(ec, A.rg.dir_y[h], -(es * A.rg.dir_x[h]));
-        }
-        A.rg_idx[out0 + r] = idx;
-        if (A.rg_feat)
+    __syncthreads();
+    const int s0 = hs[2 * tid], s1 = hs[2 * tid + 1];
+    uint32_t tot;
+    // valid counts (<= 32768) in the high half, sample counts (<= 2048) in the low half
+    const uint32_t exs = block_exclusive(((uint32_t)nv_local << 16) | (uint32_t)(s0 + s1), wtot, &tot) & 0xffffu;
+    const int nvalid = (int)(tot >> 16), ns = (int)(tot & 0xffffu);
+    const int kk = __builtin_amdgcn_readfirstlane(min(A.k, nvalid));
+    const int want = (3 * kk + 31) / 32 + 4;   // samples below U: 1.5 kk / 16, plus slack
+    if (want < ns && (int)exs <= want - 1 && want - 1 < (int)exs + s0 + s1)
+        sh_bound = (uint32_t)(want - 1 < (int)exs + s0 ? 2 * tid + 1 : 2 * tid + 2) << kDigitShift;
+    __syncthreads();
+    uint32_t U = __builtin_amdgcn_readfirstlane(sh_bound);
+
+    // ---- the keys below U: count, and compact into the list ----
+    int below = 0;
+#pragma unroll
+    for (int r = 0; r < kObsKeys; ++r)
+        below += key[r] < U;   // kNoKey is never below U
+    uint32_t nU;
+    uint32_t off = block_exclusive((uint32_t)below, wtot, &nU);
+    if (kk > 0 && (int)nU < kk) {
+        // the sample misled: every valid key stays a candidate
+        U = kAllKeys;
+        off = block_exclusive((uint32_t)nv_local, wtot, &nU);
+    }
+    const bool use_list = kk > 0 && (int)nU <= kListCap;
+    if (use_list) {
+#pragma unroll
+        for (int r = 0; r < kObsKeys; ++r)
+            if (key[r] < U)
+                list[off++] = ((uint64_t)key[r] << 32) | (uint32_t)(tid + kObsThreads * r);
+    }
+
+    ObsOut o{A.rg_idx + (orow + slot) * A.k, A.rg_feat ? A.rg_feat + (orow + slot) * A.k * 4 : nullptr,
+             A.rg.x, A.rg.y, A.rg.dir_x, A.rg.dir_y, ex, ey, es, ec};
+    bool done = kk == 0;
+    if (use_list)
+        done = topk_select<false>(ListKeys{list, (int)nU}, kk, L, o, p0);
+    if (!done)
+        topk_select<true>(RegKeys{key}, kk, L, o, p0);
+    // ---- padding ----
+    for (int r = kk + tid; r < A.k; r += kObsThreads) {
+        o.idx[r] = -1;
+        if (o.feat)
             for (int c = 0; c < 4; ++c)
-                A.rg_feat[4 * (out0 + r) + c] = f[c];
+                o.feat[4L * r + c] = 0.f;
     }
 }
 
 void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_observe, dim3(b.num_scenarios * a.E, rows), dim3(kObsThreads), 0, st, a);
+    const long blocks = (long)rows * b.num_scenarios * a.E;
+    hipLaunchKernelGGL(k_observe, dim3((unsigned)blocks), dim3(kObsThreads), 0, st, a, rows);
 }
 
 } // namespace wm

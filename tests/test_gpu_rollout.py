@@ -225,6 +225,51 @@ def test_observe_topk_and_frames(k):
     assert ok.all()
 
 
+@pytest.mark.parametrize("k", [1000, 1024])
+def test_observe_selection_inside_one_bin(k):
+    """Selections decided inside one radix bin of the squared distance: in
+    scenario 0, 2,500 road points share one location 3 m from ego 0, so more
+    than 1,024 binary32 keys are exactly equal at the k-th place and the
+    lowest indices must win; in scenario 1, 4,000 points lie on a ring of
+    radius 9.85..10.15 m around ego 0 (d2 in [97, 103], one bin of the first
+    11-bit digit); in scenario 2, 2,000 points lie on a ring 0.25 mm thick, so
+    the keys share the first two digits and many are equal."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = synth.make_scene(4, scenarios=3, objects=(8, 40), rg_points=(6000, 8000), steps=2, rg_invalid_frac=0.02)
+    st = sc.state_at(synth.T0)
+    rng = np.random.default_rng(11)
+    for s, m in ((0, 2500), (1, 4000), (2, 2000)):
+        p0, p1 = sc.rg_off[s], sc.rg_off[s + 1]
+        at = p0 + rng.choice(p1 - p0, m, replace=False)     # spread over the index range
+        g = sc.ego[s, 0]
+        ex, ey = float(st["x"][g]), float(st["y"][g])
+        if s == 0:
+            rad, ang = np.full(m, 3.0), np.full(m, 0.7)
+        elif s == 1:
+            rad, ang = rng.uniform(9.85, 10.15, m), rng.uniform(-np.pi, np.pi, m)
+        else:
+            rad, ang = rng.uniform(10.0, 10.00025, m), rng.uniform(-np.pi, np.pi, m)
+        sc.rg["x"][at] = (ex + rad * np.cos(ang)).astype(np.float32)
+        sc.rg["y"][at] = (ey + rad * np.sin(ang)).astype(np.float32)
+        sc.rg["valid"][at] = 1
+    ds = wm.upload(sc, dev)
+    S, E = sc.num_scenarios, sc.ego.shape[1]
+    maxN = ds.batch.max_objects
+    idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
+    rf = torch.empty((S * E * k * 4,), device=dev)
+    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, k, idx, rf, None)
+    torch.cuda.synchronize()
+    o_idx, o_rf, _ = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, maxN)
+    gi = idx.cpu().numpy().reshape(S, E, k)
+    # the constructed groups do decide the k-th place of ego 0
+    for s in range(S):
+        assert (o_idx[s, 0] >= 0).all()
+    np.testing.assert_array_equal(gi, o_idx)     # bit-exact
+    assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all()
+
+
 def test_observe_every_step_of_a_sequence():
     """wm_observe_seq over the logged rows equals the oracle's observation of
     each row (indices bit-exact); over a fused rollout's trajectory it equals
