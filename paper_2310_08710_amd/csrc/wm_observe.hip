@@ -33,7 +33,7 @@ constexpr uint32_t kNoKey = 0xffffffffu;                        // invalid point
 constexpr uint32_t kAllKeys = 0x80000000u;                      // above every valid key
 constexpr int kBins = 2048;                                     // first digit: key bits 20..30
 constexpr int kDigitShift = 20;
-constexpr int kHistCopies = 4;
+constexpr int kHistCopies = 2;
 constexpr int kCandCap = 1024;                                  // boundary keys ranked directly
 constexpr int kListCap = 4096;                                  // candidates compacted into LDS
 constexpr int kSampleMask = 15;                                 // points j with j % 16 == 0 are sampled
@@ -69,17 +69,30 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *wtot, 
     return off + incl - v;
 }
 
-// Number of entries of a[lo, hi) below `own`, four loads in flight.
+// Number of entries of a[lo, hi) below `own`, eight loads in flight.
 __device__ __forceinline__ int count_below(const uint64_t *a, int lo, int hi, uint64_t own)
 {
     int c = 0, q = lo;
-    for (; q + 4 <= hi; q += 4) {
-        const uint64_t a0 = a[q], a1 = a[q + 1], a2 = a[q + 2], a3 = a[q + 3];
-        c += (int)(a0 < own) + (int)(a1 < own) + (int)(a2 < own) + (int)(a3 < own);
+    for (; q + 8 <= hi; q += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = a[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            c += v[u] < own;
     }
     for (; q < hi; ++q)
         c += a[q] < own;
     return c;
+}
+
+// Sum over the wave.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+    for (int d = 32; d > 0; d >>= 1)
+        v += __shfl_xor(v, d);
+    return v;
 }
 
 struct ObsOut {
@@ -113,46 +126,60 @@ struct TopkLds {
     int *sh;             // [4] bin, before, count, boundary-list length
 };
 
-// Candidates held in registers: point j = tid + 1024 r has key[r].
-struct RegKeys {
-    const uint32_t *key;
+// Every point of the scenario as a candidate, its key recomputed from the
+// road graph at each pass (the rare fallback): point j = tid + 1024 r.
+struct AllKeys {
+    const float *rx, *ry;
+    const uint8_t *rv;
+    int P;
+    bool have;   // ego valid and P > 0
+    float ex, ey;
     template <class F> __device__ __forceinline__ void each(F &&f) const
     {
-#pragma unroll
-        for (int r = 0; r < kObsKeys; ++r)
-            f(key[r], (int)threadIdx.x + kObsThreads * r, r);
+        if (!have)
+            return;
+#pragma unroll 4
+        for (int r = 0; r < kObsKeys; ++r) {
+            // indices past the scenario's points are clamped to its last
+            // point (an in-bounds load) and give no key
+            const int j = (int)threadIdx.x + kObsThreads * r, jj = min(j, P - 1);
+            const uint32_t kq = topk_key(rx[jj], ry[jj], ex, ey);
+            f((j < P && rv[jj] != 0) ? kq : kNoKey, j, r);
+        }
     }
 };
 
-// Candidates compacted into LDS as (key << 32 | j).
+// Candidates compacted into LDS: keys and scenario-local indices.
 struct ListKeys {
-    const uint64_t *list;
+    const uint32_t *key;
+    const uint32_t *idx;
     int n;
     template <class F> __device__ __forceinline__ void each(F &&f) const
     {
-        for (int i = threadIdx.x; i < n; i += kObsThreads) {
-            const uint64_t e = list[i];
-            f((uint32_t)(e >> 32), (int)(uint32_t)e, 0);
-        }
+        for (int i = threadIdx.x; i < n; i += kObsThreads)
+            f(key[i], (int)idx[i], 0);
     }
 };
 
 // Selects and writes the kk (>= 1, <= number of candidates) smallest
 // candidates in (key, index) order; every candidate not given is larger than
 // every one given.  Returns false, having written nothing, when the boundary
-// set is over kCandCap equal keys and the candidates are not the registers
-// (whose fixed index order that case needs).  Work-group-wide; every thread
-// calls it with the same arguments.
+// set is over kCandCap equal keys and the candidates are not AllKeys (whose
+// fixed index order that case needs).  Work-group-wide; every thread calls it
+// with the same arguments.
 template <bool kReg, class Src>
-__device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLds &L, const ObsOut &o, int p0)
+__device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLds &L, const ObsOut &o, int p0,
+                                            bool cleared)
 {
     const int tid = threadIdx.x;
-    __syncthreads();   // earlier readers of the LDS arrays are done
-    for (int b = tid; b < kHistCopies * kBins; b += kObsThreads)
-        L.hist[b] = 0;
-    if (tid < 4)
-        L.sh[tid] = 0;
-    __syncthreads();
+    if (!cleared) {
+        __syncthreads();   // earlier readers of the LDS arrays are done
+        for (int b = tid; b < kHistCopies * kBins; b += kObsThreads)
+            L.hist[b] = 0;
+        if (tid < 4)
+            L.sh[tid] = 0;
+        __syncthreads();
+    }
 
     // ---- first digit: histogram, prefix, the bin holding the kk-th key ----
     int *myhist = L.hist + kBins * (tid & (kHistCopies - 1));
@@ -249,7 +276,8 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
 
     // ---- the boundary set: rank among itself, keep the lowest `need` ----
     if (direct) {
-        for (int c = tid; c < nB; c += kObsThreads) {
+        // on the last threads: the first ones rank the keys below the boundary
+        for (int c = kObsThreads - 1 - tid; c < nB; c += kObsThreads) {
             const uint64_t own = L.cand[c];
             const int before = count_below(L.cand, 0, nB, own);
             if (before < need) {
@@ -299,7 +327,8 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
     return true;
 }
 
-__global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A, int rows)
+__global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_observe(ObserveArgs A,
+                                                                                                   int rows)
 {
     // Work item w = (s * rows + row) * E + e.  Work-groups are dispatched to
     // the eight XCDs in turn; each XCD takes a contiguous range of w, so the
@@ -313,15 +342,16 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A, int rows
     const int slot = s * A.E + e;
     const long so = (long)row * A.n, orow = (long)row * A.S * A.E;
 
+    // 72 KB: two work-groups fit on a CU
     __shared__ int hist[kHistCopies * kBins];
     __shared__ int base[kBins + 1];
     __shared__ uint64_t sel[WM_MAX_TOPK];
-    __shared__ uint64_t cand[kCandCap];
-    __shared__ uint64_t list[kListCap];
-    __shared__ int hs[kBins];                   // first-digit histogram of the sampled keys
+    __shared__ uint64_t cand[kCandCap];         // first the sample histogram (2048 ints)
+    __shared__ uint32_t lkey[kListCap], lidx[kListCap];
+    int *hs = (int *)cand;                      // first-digit histogram of the sampled keys
     __shared__ uint32_t wtot[kObsThreads / 64];
     __shared__ int sh[4];
-    __shared__ uint32_t sh_bound;
+    __shared__ uint32_t sh_bound, sh_nvalid, sh_nU;
     const TopkLds L{hist, base, sel, cand, wtot, sh};
     const int tid = threadIdx.x;
     const int o0 = A.obj_off[s], N = A.obj_off[s + 1] - o0;
@@ -333,8 +363,15 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A, int rows
     sincosf(eyaw, &es, &ec);
     for (int b = tid; b < kBins; b += kObsThreads)
         hs[b] = 0;
-    if (tid == 0)
+    for (int b = tid; b < kHistCopies * kBins; b += kObsThreads)
+        hist[b] = 0;
+    if (tid < 4)
+        sh[tid] = 0;
+    if (tid == 0) {
         sh_bound = kAllKeys;
+        sh_nvalid = 0;
+        sh_nU = 0;
+    }
 
     // ---- objects in the ego frame ----
     if (A.obj_feat) {
@@ -387,46 +424,63 @@ __global__ __launch_bounds__(kObsThreads) void k_observe(ObserveArgs A, int rows
         if ((tid & kSampleMask) == 0 && key[r] != kNoKey)
             atomicAdd(&hs[key[r] >> kDigitShift], 1);
     }
+    const uint32_t nv_wave = wave_sum((uint32_t)nv_local);
+    if ((tid & 63) == 0)
+        atomicAdd(&sh_nvalid, nv_wave);
     __syncthreads();
+    const int nvalid = __builtin_amdgcn_readfirstlane(sh_nvalid);
+    const int kk = min(A.k, nvalid);
     const int s0 = hs[2 * tid], s1 = hs[2 * tid + 1];
-    uint32_t tot;
-    // valid counts (<= 32768) in the high half, sample counts (<= 2048) in the low half
-    const uint32_t exs = block_exclusive(((uint32_t)nv_local << 16) | (uint32_t)(s0 + s1), wtot, &tot) & 0xffffu;
-    const int nvalid = (int)(tot >> 16), ns = (int)(tot & 0xffffu);
-    const int kk = __builtin_amdgcn_readfirstlane(min(A.k, nvalid));
+    uint32_t ns;
+    const int exs = (int)block_exclusive((uint32_t)(s0 + s1), wtot, &ns);
     const int want = (3 * kk + 31) / 32 + 4;   // samples below U: 1.5 kk / 16, plus slack
-    if (want < ns && (int)exs <= want - 1 && want - 1 < (int)exs + s0 + s1)
-        sh_bound = (uint32_t)(want - 1 < (int)exs + s0 ? 2 * tid + 1 : 2 * tid + 2) << kDigitShift;
+    if (want < (int)ns && exs <= want - 1 && want - 1 < exs + s0 + s1)
+        sh_bound = (uint32_t)(want - 1 < exs + s0 ? 2 * tid + 1 : 2 * tid + 2) << kDigitShift;
     __syncthreads();
-    uint32_t U = __builtin_amdgcn_readfirstlane(sh_bound);
+    const uint32_t U = __builtin_amdgcn_readfirstlane(sh_bound);
 
-    // ---- the keys below U: count, and compact into the list ----
-    int below = 0;
-#pragma unroll
-    for (int r = 0; r < kObsKeys; ++r)
-        below += key[r] < U;   // kNoKey is never below U
-    uint32_t nU;
-    uint32_t off = block_exclusive((uint32_t)below, wtot, &nU);
-    if (kk > 0 && (int)nU < kk) {
-        // the sample misled: every valid key stays a candidate
-        U = kAllKeys;
-        off = block_exclusive((uint32_t)nv_local, wtot, &nU);
-    }
-    const bool use_list = kk > 0 && (int)nU <= kListCap;
-    if (use_list) {
+    // ---- the keys below U, appended to the list (any order: the
+    // selection ranks by (key, index)); one list atomic per wave ----
+    if (kk > 0) {
+        int below = 0;
 #pragma unroll
         for (int r = 0; r < kObsKeys; ++r)
-            if (key[r] < U)
-                list[off++] = ((uint64_t)key[r] << 32) | (uint32_t)(tid + kObsThreads * r);
+            below += key[r] < U;   // kNoKey is never below U
+        const int lane = tid & 63;
+        int incl = below;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl, d);
+            if (lane >= d)
+                incl += u;
+        }
+        int wbase = 0;
+        if (lane == 63)
+            wbase = (int)atomicAdd(&sh_nU, (uint32_t)incl);
+        int off = __shfl(wbase, 63) + incl - below;
+#pragma unroll
+        for (int r = 0; r < kObsKeys; ++r)
+            if (key[r] < U) {
+                if (off < kListCap) {
+                    lkey[off] = key[r];
+                    lidx[off] = (uint32_t)(tid + kObsThreads * r);
+                }
+                ++off;
+            }
     }
+    __syncthreads();
+    const int nU = __builtin_amdgcn_readfirstlane((int)sh_nU);
 
     ObsOut o{A.rg_idx + (orow + slot) * A.k, A.rg_feat ? A.rg_feat + (orow + slot) * A.k * 4 : nullptr,
              A.rg.x, A.rg.y, A.rg.dir_x, A.rg.dir_y, ex, ey, es, ec};
+    // the list holds the nU smallest keys; it serves when that is at least
+    // kk and fits (otherwise, rarely: the sample misled, or too many keys
+    // share the bound's bin), every point is a candidate
     bool done = kk == 0;
-    if (use_list)
-        done = topk_select<false>(ListKeys{list, (int)nU}, kk, L, o, p0);
+    if (!done && nU >= kk && nU <= kListCap)
+        done = topk_select<false>(ListKeys{lkey, lidx, nU}, kk, L, o, p0, true);
     if (!done)
-        topk_select<true>(RegKeys{key}, kk, L, o, p0);
+        topk_select<true>(AllKeys{A.rg.x + p0, A.rg.y + p0, A.rg.valid + p0, P, ego_valid && P > 0, ex, ey}, kk,
+                          L, o, p0, false);
     // ---- padding ----
     for (int r = kk + tid; r < A.k; r += kObsThreads) {
         o.idx[r] = -1;
