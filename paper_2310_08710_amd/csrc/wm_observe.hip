@@ -2,26 +2,27 @@
 // and the k road points nearest to the ego, exact, ascending by
 // (binary32 squared distance, index).
 //
-// One 1024-thread work-group per (row, scenario, ego).  Each thread keeps up
-// to 32 keys in registers (points j = tid + 1024 r), so a scenario's road
-// graph is read once per ego.  The keys are non-negative floats, whose bit
-// patterns order like their values.
-//   1. Every 16th point is sampled; a histogram of the samples' first digit
-//      (key bits 20..30: exponent and three mantissa bits) gives a bound U
-//      below which about 1.5 k keys should lie.  The keys below U are counted
-//      exactly; if there are at least k of them (and no more than an LDS list
-//      holds), they are compacted into that list and the rest are never
-//      touched again.  Otherwise every key stays a candidate.
-//   2. A first-digit histogram of the candidates locates the bin b holding
-//      the k-th key; every candidate below that bin is selected.
-//   3. The keys of bin b (rarely more than a few hundred; otherwise further
-//      10-bit digits narrow it first) are ranked among themselves by
-//      (key, index), and the lowest ones fill the last places.
+// One 1024-thread work-group per (row, scenario, ego); two fit on a CU.  Each
+// thread keeps up to 32 keys in registers (points j = tid + 1024 r), so a
+// scenario's road graph is read once per ego.  The keys are non-negative
+// floats, whose bit patterns order like their values.
+//   1. Every 16th point is sampled; a histogram of the samples' top bits
+//      (exponent and three mantissa bits) gives a bound U below which about
+//      1.5 k keys should lie.  The keys below U are appended to an LDS list
+//      (one atomic per wave).  If the list holds at least k keys and did not
+//      overflow, the rest are never touched again; otherwise (rarely) every
+//      point is a candidate, its key recomputed from the road graph.
+//   2. A histogram of the candidates' first digit (key bits 19..30: exponent
+//      and four mantissa bits, 4096 bins) locates the bin b holding the k-th
+//      key; every candidate below that bin is selected.
+//   3. The keys of bin b (rarely more than a few hundred; otherwise the next
+//      digits narrow it first) are ranked among themselves by (key, index),
+//      and the lowest ones fill the last places.
 //   4. The selected keys below bin b are scattered into LDS grouped by their
 //      bin, whose output range is known from the histogram's prefix sum, and
 //      each one's place is the start of its bin plus the number of keys of
 //      that bin that precede it.
-// No sorting network: about fourteen work-group barriers per ego.
+// No sorting network: nine work-group barriers per ego on the list path.
 #include "wm_device.h"
 #include "wm_internal.h"
 
@@ -31,12 +32,14 @@ constexpr int kObsThreads = 1024;
 constexpr int kObsKeys = WM_MAX_OBSERVE_POINTS / kObsThreads;  // 32
 constexpr uint32_t kNoKey = 0xffffffffu;                        // invalid point
 constexpr uint32_t kAllKeys = 0x80000000u;                      // above every valid key
-constexpr int kBins = 2048;                                     // first digit: key bits 20..30
-constexpr int kDigitShift = 20;
-constexpr int kHistCopies = 2;
+constexpr int kBins = 4096;                                     // first digit: key bits 19..30
+constexpr int kDigitShift = 19;
+constexpr int kHistCopies = 1;
+constexpr int kBinsPerThread = kBins / kObsThreads;
+constexpr int kSampleBins = 2048;                               // sample digit: key bits 20..30
+constexpr int kSampleShift = 20;
 constexpr int kCandCap = 1024;                                  // boundary keys ranked directly
-constexpr int kListCap = 4096;                                  // candidates compacted into LDS
-constexpr int kSampleMask = 15;                                 // points j with j % 16 == 0 are sampled
+constexpr int kListCap = 3072;                                  // candidates compacted into LDS
 
 __device__ __forceinline__ uint32_t topk_key(float qx, float qy, float ex, float ey)
 {
@@ -182,31 +185,37 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
     }
 
     // ---- first digit: histogram, prefix, the bin holding the kk-th key ----
-    int *myhist = L.hist + kBins * (tid & (kHistCopies - 1));
+    int *myhist = L.hist + kBins * (tid % kHistCopies);
     src.each([&](uint32_t k, int, int) {
         if (k != kNoKey)
             atomicAdd(&myhist[k >> kDigitShift], 1);
     });
     __syncthreads();
-    int c0 = 0, c1 = 0;   // bins 2 tid and 2 tid + 1, copies summed
-    for (int c = 0; c < kHistCopies; ++c) {
-        c0 += L.hist[kBins * c + 2 * tid];
-        c1 += L.hist[kBins * c + 2 * tid + 1];
+    constexpr int BPT = kBinsPerThread;
+    int c[BPT], csum = 0;   // this thread's bins BPT tid .. BPT tid + BPT - 1, copies summed
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        c[i] = 0;
+        for (int cp = 0; cp < kHistCopies; ++cp)
+            c[i] += L.hist[kBins * cp + BPT * tid + i];
+        csum += c[i];
     }
     uint32_t tot;
-    const int ex0 = (int)block_exclusive((uint32_t)(c0 + c1), L.wtot, &tot);
-    L.base[2 * tid] = ex0;
-    L.base[2 * tid + 1] = ex0 + c0;
+    const int ex0 = (int)block_exclusive((uint32_t)csum, L.wtot, &tot);
     if (tid == 0)
         L.base[kBins] = (int)tot;
-    // only this thread read its two bins: they become its scatter cursors
-    L.hist[2 * tid] = ex0;
-    L.hist[2 * tid + 1] = ex0 + c0;
-    if (ex0 <= kk - 1 && kk - 1 < ex0 + c0 + c1) {
-        const bool first = kk - 1 < ex0 + c0;
-        L.sh[0] = 2 * tid + (first ? 0 : 1);
-        L.sh[1] = first ? ex0 : ex0 + c0;
-        L.sh[2] = first ? c0 : c1;
+    int run = ex0;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        // only this thread read its bins: they become its scatter cursors
+        L.base[BPT * tid + i] = run;
+        L.hist[BPT * tid + i] = run;
+        if (run <= kk - 1 && kk - 1 < run + c[i]) {
+            L.sh[0] = BPT * tid + i;
+            L.sh[1] = run;
+            L.sh[2] = c[i];
+        }
+        run += c[i];
     }
     __syncthreads();
     // block-uniform from here on (read into scalar registers)
@@ -218,19 +227,22 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
     // ---- a boundary bin too large to rank directly: narrow it by the
     // next 10-bit digits ----
     if (nB > kCandCap) {
-        for (int sh = 10; sh >= 0 && nB > kCandCap; sh -= 10) {
+        for (int pass = 0; pass < 2 && nB > kCandCap; ++pass) {
+            // the next 10 bits below the first digit, then the rest
+            const int sh = pass == 0 ? kDigitShift - 10 : 0;
+            const uint32_t dm = pass == 0 ? 1023u : (1u << (kDigitShift - 10)) - 1u;
             __syncthreads();
-            for (int c = 0; c < kHistCopies; ++c)
-                L.hist[kBins * c + tid] = 0;
+            for (int cp = 0; cp < kHistCopies; ++cp)
+                L.hist[kBins * cp + tid] = 0;
             __syncthreads();
             src.each([&](uint32_t k, int, int) {
                 if ((k & pmask) == prefix)   // never true for kNoKey: prefix < 2^31
-                    atomicAdd(&myhist[(k >> sh) & 1023], 1);
+                    atomicAdd(&myhist[(k >> sh) & dm], 1);
             });
             __syncthreads();
             int cnt = 0;
-            for (int c = 0; c < kHistCopies; ++c)
-                cnt += L.hist[kBins * c + tid];
+            for (int cp = 0; cp < kHistCopies; ++cp)
+                cnt += L.hist[kBins * cp + tid];
             uint32_t t2;
             const int exb = (int)block_exclusive((uint32_t)cnt, L.wtot, &t2);
             const int rank = kk - 1 - c_less;
@@ -241,15 +253,16 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
             }
             __syncthreads();
             prefix |= (uint32_t)__builtin_amdgcn_readfirstlane(L.sh[0]) << sh;
-            pmask |= 1023u << sh;
+            pmask |= dm << sh;
             c_less += __builtin_amdgcn_readfirstlane(L.sh[1]);
             nB = __builtin_amdgcn_readfirstlane(L.sh[2]);
         }
         if (!kReg && nB > kCandCap)
             return false;
         __syncthreads();
-        L.hist[2 * tid] = L.base[2 * tid];
-        L.hist[2 * tid + 1] = L.base[2 * tid + 1];
+#pragma unroll
+        for (int i = 0; i < BPT; ++i)
+            L.hist[BPT * tid + i] = L.base[BPT * tid + i];
         if (tid == 0)
             L.sh[3] = 0;
         __syncthreads();
@@ -346,9 +359,10 @@ __global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))
     __shared__ int hist[kHistCopies * kBins];
     __shared__ int base[kBins + 1];
     __shared__ uint64_t sel[WM_MAX_TOPK];
-    __shared__ uint64_t cand[kCandCap];         // first the sample histogram (2048 ints)
+    __shared__ uint64_t cand[kCandCap];         // first the sample histogram
     __shared__ uint32_t lkey[kListCap], lidx[kListCap];
-    int *hs = (int *)cand;                      // first-digit histogram of the sampled keys
+    static_assert(kSampleBins * sizeof(int) <= kCandCap * sizeof(uint64_t), "sample histogram overlays cand");
+    int *hs = (int *)cand;                      // sample-digit histogram of the sampled keys
     __shared__ uint32_t wtot[kObsThreads / 64];
     __shared__ int sh[4];
     __shared__ uint32_t sh_bound, sh_nvalid, sh_nU;
@@ -361,7 +375,7 @@ __global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))
     const float ex = A.st.x[so + g], ey = A.st.y[so + g], eyaw = A.st.yaw[so + g];
     float es, ec;
     sincosf(eyaw, &es, &ec);
-    for (int b = tid; b < kBins; b += kObsThreads)
+    for (int b = tid; b < kSampleBins; b += kObsThreads)
         hs[b] = 0;
     for (int b = tid; b < kHistCopies * kBins; b += kObsThreads)
         hist[b] = 0;
@@ -416,13 +430,13 @@ __global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))
     }
     __syncthreads();   // hs cleared
 
-    // ---- sample: valid count and the bound U ----
+    // ---- sample (every 16th point): valid count and the bound U ----
     int nv_local = 0;
 #pragma unroll
     for (int r = 0; r < kObsKeys; ++r) {
         nv_local += key[r] != kNoKey;
-        if ((tid & kSampleMask) == 0 && key[r] != kNoKey)
-            atomicAdd(&hs[key[r] >> kDigitShift], 1);
+        if ((tid & 15) == 0 && key[r] != kNoKey)
+            atomicAdd(&hs[key[r] >> kSampleShift], 1);
     }
     const uint32_t nv_wave = wave_sum((uint32_t)nv_local);
     if ((tid & 63) == 0)
@@ -435,7 +449,7 @@ __global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))
     const int exs = (int)block_exclusive((uint32_t)(s0 + s1), wtot, &ns);
     const int want = (3 * kk + 31) / 32 + 4;   // samples below U: 1.5 kk / 16, plus slack
     if (want < (int)ns && exs <= want - 1 && want - 1 < exs + s0 + s1)
-        sh_bound = (uint32_t)(want - 1 < exs + s0 ? 2 * tid + 1 : 2 * tid + 2) << kDigitShift;
+        sh_bound = (uint32_t)(want - 1 < exs + s0 ? 2 * tid + 1 : 2 * tid + 2) << kSampleShift;
     __syncthreads();
     const uint32_t U = __builtin_amdgcn_readfirstlane(sh_bound);
 

@@ -270,6 +270,37 @@ def test_observe_selection_inside_one_bin(k):
     assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all()
 
 
+def test_observe_small_and_odd_point_counts():
+    """Scenarios of 1, 2, 3, 5, 4,097 and 6,143 road points (groups of four
+    points are read together; the last group is partial), k = 4 and k = 1000,
+    so that k exceeds the valid points of some scenarios; some points invalid."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    counts = [1, 2, 3, 5, 4097, 6143]
+    sc = synth.make_scene(4, scenarios=len(counts), objects=(3, 9), rg_points=(24, 24), steps=2)
+    rng = np.random.default_rng(5)
+    P = np.asarray(counts)
+    sc.rg_off = np.concatenate([[0], np.cumsum(P)]).astype(np.int32)
+    tot = int(P.sum())
+    sc.rg = {"x": rng.uniform(-60, 60, tot).astype(np.float32), "y": rng.uniform(-60, 60, tot).astype(np.float32),
+             "dir_x": np.ones(tot, np.float32), "dir_y": np.zeros(tot, np.float32),
+             "type": np.ones(tot, np.int8), "valid": (rng.random(tot) > 0.1).astype(np.uint8)}
+    sc.rg["valid"][0] = 1
+    st = sc.state_at(synth.T0)
+    ds = wm.upload(sc, dev)
+    S, E = sc.num_scenarios, sc.ego.shape[1]
+    maxN = ds.batch.max_objects
+    for k in (4, 1000):
+        idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
+        rf = torch.empty((S * E * k * 4,), device=dev)
+        wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, k, idx, rf, None)
+        torch.cuda.synchronize()
+        o_idx, o_rf, _ = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, maxN)
+        np.testing.assert_array_equal(idx.cpu().numpy().reshape(S, E, k), o_idx, err_msg="k=%d" % k)
+        assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all(), k
+
+
 def test_observe_every_step_of_a_sequence():
     """wm_observe_seq over the logged rows equals the oracle's observation of
     each row (indices bit-exact); over a fused rollout's trajectory it equals
