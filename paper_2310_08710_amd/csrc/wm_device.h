@@ -121,17 +121,28 @@ __device__ __forceinline__ float sat_margin(const Box &a, const Box &b)
 // with L_k > s (yaw along the shorter arc between the logged yaws), or row
 // T's pose when there is no such row.  One path is 16 (T + 1) contiguous
 // bytes, so the search and the interpolation stay in a few cache lines.
-__device__ __forceinline__ void idm_pose(const float4 *__restrict__ path, int T, float s, float &x, float &y,
-                                         float &yaw)
+
+// Index lo of the first path point 1..T whose arc length w(k) exceeds s
+// (T + 1: none); w non-decreasing.
+template <class Wf>
+__device__ __forceinline__ int idm_segment(Wf w, int T, float s)
 {
     int lo = 1, hi = T + 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (path[mid].w > s)
+        if (w(mid) > s)
             hi = mid;
         else
             lo = mid + 1;
     }
+    return lo;
+}
+
+// The pose at arc length s given its segment lo (idm_segment): linear
+// between path points lo - 1 and lo, the last point past the end.
+__device__ __forceinline__ void idm_interp(const float4 *__restrict__ path, int T, int lo, float s, float &x, float &y,
+                                           float &yaw)
+{
     if (lo > T) {
         const float4 r = path[T];
         x = r.x;
@@ -144,6 +155,12 @@ __device__ __forceinline__ void idm_pose(const float4 *__restrict__ path, int T,
     x = __builtin_fmaf(lam, b.x - a.x, a.x);
     y = __builtin_fmaf(lam, b.y - a.y, a.y);
     yaw = __builtin_fmaf(lam, wrap_angle(b.z - a.z), a.z);
+}
+
+__device__ __forceinline__ void idm_pose(const float4 *__restrict__ path, int T, float s, float &x, float &y,
+                                         float &yaw)
+{
+    idm_interp(path, T, idm_segment([&](int k) { return path[k].w; }, T, s), s, x, y, yaw);
 }
 
 // IDM acceleration for speed v; `lead` selects the interaction term with gap

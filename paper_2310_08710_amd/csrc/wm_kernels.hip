@@ -678,85 +678,151 @@ __global__ __launch_bounds__(1024) void k_offroad(OffroadArgs A)
 // object.
 constexpr int kIdmMaskMaxN = 256;
 
+// Per-wave LDS scratch of the lead search (floats): poses x, y, yaw of up
+// to WM_MAX_IDM_POSES lookahead poses, then the candidate list (ints).
+constexpr int kIdmPoseScratch = 3 * 64;
+static_assert(WM_MAX_IDM_POSES <= 64, "one lane per lookahead pose");
+static_assert((kIdmPoseScratch + WM_MAX_OBJECTS) * 4 <= kStageBytes + 256 * 20,
+              "poses and candidates of a wave fit in that wave's share of the off-road scratch");
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int d = 32; d > 0; d >>= 1)
+        v = min(v, __shfl_xor(v, d));
+    return v;
+}
+
 // IDM sim agents, per step from the states at t-1 in LDS: the lead of every
 // agent (the first lookahead pose, then the lowest object index, whose box
-// overlaps another valid object's current box) by an LDS atomic minimum over
-// (agent, pose) work items, then each agent's acceleration into ia[].  All
-// poses of agent i lie within M * step (arc length) of its pose at sig[i], so
-// only objects within M * step + r_i + r_j of that point (r: half diagonal)
-// can overlap one of them; with maxN <= kIdmMaskMaxN those candidates are
-// collected first as a bit mask per agent.  Contains four block barriers.
+// overlaps another valid object's current box), then each agent's
+// acceleration into ia[].  All poses of agent i lie within M * step (arc
+// length) of its pose at sig[i], so only objects within M * step + r_i + r_j
+// of that point (r: half diagonal) can overlap one of them; with maxN <=
+// kIdmMaskMaxN those candidates are collected first as a bit mask per agent,
+// one 32-bit word per half-wave ballot.  Then one wave per agent: lane m
+// computes lookahead pose m + 1, the candidates are listed in ascending
+// index order, and the (pose, candidate) pairs are tested 64 at a time in
+// pose-major order, so the first pass with an overlap holds the lead (a
+// wave minimum of pose * 2048 + index).  wscr: the off-road scratch, unused
+// at this point of the step.  Contains three block barriers.
 __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, int o0, int N, const float *sig, float *ia,
-                                          int *lk, const uint8_t *agent, float *pc, uint32_t *mask)
+                                          int *lk, const uint8_t *agent, float *pc, uint32_t *mask, float *wscr)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = nthr >> 6;
     const int M = A.idm.lookahead_poses;
     const bool use_mask = A.maxN <= kIdmMaskMaxN;
     const int W = (N + 31) >> 5;
+    float *rad = ia;   // circumradius per object, until the accelerations are written
     for (int i = tid; i < N; i += nthr) {
-        lk[i] = 0x7fffffff;
+        rad[i] = 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i]));
         if (use_mask && agent[i]) {
             float yaw;
             idm_pose(A.idmP + (long)(o0 + i) * (A.T + 1), A.T, sig[i], pc[2 * i], pc[2 * i + 1], yaw);
         }
     }
-    if (use_mask)
-        for (int k = tid; k < N * W; k += nthr)
-            mask[k] = 0u;
     __syncthreads();
     const float reach = (float)M * A.idm.lookahead_step;
     if (use_mask) {
-        for (int it = tid; it < N * N; it += nthr) {
-            const int i = it / N, j = it - i * N;
-            if (!agent[i] || j == i || !L.valid[j])
-                continue;
-            const float dx = L.x[j] - pc[2 * i], dy = L.y[j] - pc[2 * i + 1];
-            const float rr = reach + 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i])) +
-                             0.5f * sqrtf(__builtin_fmaf(L.wid[j], L.wid[j], L.len[j] * L.len[j])) + 1e-2f;
-            if (__builtin_fmaf(dy, dy, dx * dx) <= rr * rr)
-                atomicOr(&mask[i * W + (j >> 5)], 1u << (j & 31));
+        // word q = (agent i, objects 32 w .. 32 w + 31): lane b of a half-wave
+        // tests object 32 w + b, and the half-wave's ballot is the word
+        const int half = lane >> 5, bit = lane & 31;
+        for (int q = 2 * wv + half; q < N * W; q += 2 * nw) {
+            const int i = q / W, j = 32 * (q - i * W) + bit;
+            bool hit = false;
+            if (agent[i] && j < N && j != i && L.valid[j]) {
+                const float dx = L.x[j] - pc[2 * i], dy = L.y[j] - pc[2 * i + 1];
+                const float rr = reach + rad[i] + rad[j] + 1e-2f;
+                hit = __builtin_fmaf(dy, dy, dx * dx) <= rr * rr;
+            }
+            const uint64_t b = __ballot(hit);
+            if (bit == 0)
+                mask[q] = (uint32_t)(b >> (32 * half));
         }
         __syncthreads();
     }
-    for (int it = tid; it < N * M; it += nthr) {
-        const int i = it / M, m = it - i * M + 1;
+    // a wave's share of the scratch: poses, candidate list, then (when it
+    // fits) the agent's path arc lengths for an LDS search
+    const int per_wave = (int)(scan_lds_bytes(A.G, A.CW) / 4 / nw);
+    float *px = wscr + (size_t)wv * per_wave, *py = px + 64, *pyw = px + 128;
+    int *cl = (int *)(px + kIdmPoseScratch);
+    float *wcol = px + kIdmPoseScratch + A.maxN;
+    const bool col_lds = kIdmPoseScratch + A.maxN + A.T + 1 <= per_wave;
+    const float step = A.idm.lookahead_step;
+    for (int i = wv; i < N; i += nw) {   // one agent per wave (uniform)
         if (!agent[i])
             continue;
-        const long g = o0 + i;
-        const float sm = __builtin_fmaf((float)m, A.idm.lookahead_step, sig[i]);
-        const float4 *path = A.idmP + g * (A.T + 1);
-        if (sm > path[A.T].w)
-            continue;
-        float px, py, pyaw, ps, pcs;
-        idm_pose(path, A.T, sm, px, py, pyaw);
-        sincosf(pyaw, &ps, &pcs);
-        const Box a{px, py, pcs, ps, 0.5f * L.len[i], 0.5f * L.wid[i]};
-        const float ra = 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i]));
-        // objects in ascending index order; the first overlap is this pose's
-        // lowest index
-        for (int w = 0; w < W; ++w) {
-            uint32_t bits = use_mask ? mask[i * W + w] : 0xffffffffu;
-            bool hit = false;
-            while (bits) {
-                const int j = 32 * w + __builtin_ctz(bits);
-                bits &= bits - 1u;
-                if (j >= N || j == i || !L.valid[j])
-                    continue;
+        const float4 *path = A.idmP + (long)(o0 + i) * (A.T + 1);
+        if (col_lds) {
+            for (int k = lane; k <= A.T; k += 64)
+                wcol[k] = path[k].w;
+            __builtin_amdgcn_wave_barrier();
+        }
+        // lookahead pose m = lane + 1, if it lies on the path
+        const int m = lane + 1;
+        const float sm = __builtin_fmaf((float)m, step, sig[i]);
+        const bool live = m <= M && sm <= path[A.T].w;
+        float x = 0.f, y = 0.f, yaw = 0.f;
+        if (live) {
+            const int lo = col_lds ? idm_segment([&](int k) { return wcol[k]; }, A.T, sm)
+                                   : idm_segment([&](int k) { return path[k].w; }, A.T, sm);
+            idm_interp(path, A.T, lo, sm, x, y, yaw);
+        }
+        px[lane] = x;
+        py[lane] = y;
+        pyw[lane] = yaw;
+        const int nlive = __popcll(__ballot(live));   // poses 1..nlive (arc length grows with m)
+        // candidates in ascending index order
+        int nc = 0;
+        for (int w0 = 0; w0 < W; w0 += 2) {
+            const int w = w0 + (lane >> 5), j = 32 * w + (lane & 31);
+            bool c = false;
+            if (w < W && j < N && j != i && L.valid[j])
+                c = use_mask ? ((mask[i * W + w] >> (lane & 31)) & 1u) != 0u : true;
+            const uint64_t bal = __ballot(c);
+            if (c)
+                cl[nc + __popcll(bal & ((1ull << lane) - 1ull))] = j;
+            nc += __popcll(bal);
+        }
+        __builtin_amdgcn_wave_barrier();   // the wave's LDS writes above precede its reads below
+        const int npair = nlive * nc;
+        const float rinv = 1.0f / (float)max(nc, 1);
+        const float ra = rad[i];
+        int lead = 0x7fffffff;
+        for (int p0 = 0; p0 < npair; p0 += 64) {
+            const int pr = p0 + lane;
+            int key = 0x7fffffff;
+            if (pr < npair) {
+                int mi = (int)(((float)pr + 0.5f) * rinv), q = pr - mi * nc;   // pose index, candidate slot
+                if (q < 0) {
+                    --mi;
+                    q += nc;
+                } else if (q >= nc) {
+                    ++mi;
+                    q -= nc;
+                }
+                const int j = cl[q];
+                const float ax = px[mi], ay = py[mi];
                 // boxes lie within their circumscribed circles
-                const float dx = L.x[j] - px, dy = L.y[j] - py;
-                const float rr = ra + 0.5f * sqrtf(__builtin_fmaf(L.wid[j], L.wid[j], L.len[j] * L.len[j])) + 1e-3f;
-                if (__builtin_fmaf(dy, dy, dx * dx) > rr * rr)
-                    continue;
-                const Box b{L.x[j], L.y[j], L.c[j], L.s[j], 0.5f * L.len[j], 0.5f * L.wid[j]};
-                if (sat_margin(a, b) > 0.f) {
-                    atomicMin(&lk[i], m * 2048 + j);
-                    hit = true;
-                    break;
+                const float dx = L.x[j] - ax, dy = L.y[j] - ay;
+                const float rr = ra + rad[j] + 1e-3f;
+                if (__builtin_fmaf(dy, dy, dx * dx) <= rr * rr) {
+                    float ps, pcs;
+                    sincosf(pyw[mi], &ps, &pcs);
+                    const Box a{ax, ay, pcs, ps, 0.5f * L.len[i], 0.5f * L.wid[i]};
+                    const Box b{L.x[j], L.y[j], L.c[j], L.s[j], 0.5f * L.len[j], 0.5f * L.wid[j]};
+                    if (sat_margin(a, b) > 0.f)
+                        key = (mi + 1) * 2048 + j;
                 }
             }
-            if (hit)
+            if (__ballot(key != 0x7fffffff)) {   // later passes hold only later poses
+                lead = wave_min(key);
                 break;
+            }
         }
+        if (lane == 0)
+            lk[i] = lead;
+        __builtin_amdgcn_wave_barrier();   // reads of this agent's scratch precede the next agent's writes
     }
     __syncthreads();
     for (int i = tid; i < N; i += nthr) {
@@ -893,7 +959,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int t = 1; t <= A.T; ++t) {
             const long row = (long)t * n, arow = (long)(t - 1) * n;
             if (A.has_idm)
-                idm_leads(A, L, o0, N, sig, ia, lk, agent, pc, mask);
+                idm_leads(A, L, o0, N, sig, ia, lk, agent, pc, mask, (float *)C.stage);
             for (int i = tid; i < N; i += nthr) {
                 const long g = o0 + i;
                 const float pvx = L.vx[i], pvy = L.vy[i], pyaw = L.yaw[i];
