@@ -270,10 +270,45 @@ def test_observe_selection_inside_one_bin(k):
     assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all()
 
 
+def test_observe_when_the_sampled_bound_misleads():
+    """Every 16th road point (the ones the kernel samples to bound the k-th
+    distance) lies within 5 m of ego 0 and every other point 60..80 m away:
+    the bound then admits fewer than k points, and the selection must fall
+    back to every point.  Indices bit-exact against the oracle."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = synth.make_scene(4, scenarios=2, objects=(8, 16), rg_points=(8000, 9000), steps=2)
+    st = sc.state_at(synth.T0)
+    rng = np.random.default_rng(13)
+    for s in range(sc.num_scenarios):
+        p0, p1 = sc.rg_off[s], sc.rg_off[s + 1]
+        g = sc.ego[s, 0]
+        j = np.arange(p1 - p0)
+        rad = np.where(j % 16 == 0, rng.uniform(0.5, 5.0, j.size), rng.uniform(60.0, 80.0, j.size))
+        ang = rng.uniform(-np.pi, np.pi, j.size)
+        sc.rg["x"][p0:p1] = (st["x"][g] + rad * np.cos(ang)).astype(np.float32)
+        sc.rg["y"][p0:p1] = (st["y"][g] + rad * np.sin(ang)).astype(np.float32)
+        sc.rg["valid"][p0:p1] = 1
+    ds = wm.upload(sc, dev)
+    S, E, k = sc.num_scenarios, sc.ego.shape[1], 1000
+    idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
+    rf = torch.empty((S * E * k * 4,), device=dev)
+    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, k, idx, rf, None)
+    torch.cuda.synchronize()
+    o_idx, o_rf, _ = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, ds.batch.max_objects)
+    # ego 0 sees its 500-odd near points first, then far ones
+    assert ((o_idx[:, 0, :400] % 16) == 0).all() and ((o_idx[:, 0, -100:] % 16) != 0).any()
+    np.testing.assert_array_equal(idx.cpu().numpy().reshape(S, E, k), o_idx)
+    assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all()
+
+
 def test_observe_small_and_odd_point_counts():
-    """Scenarios of 1, 2, 3, 5, 4,097 and 6,143 road points (groups of four
-    points are read together; the last group is partial), k = 4 and k = 1000,
-    so that k exceeds the valid points of some scenarios; some points invalid."""
+    """Scenarios of 1, 2, 3, 5, 4,097 and 6,143 road points (the last round
+    of the 1024-thread work-group is partial; loads past a scenario's end are
+    clamped), k = 4 and k = 1000, so that k exceeds the valid points of some
+    scenarios; some points invalid.  Again with the road-graph arrays 4 bytes
+    past a 16-byte boundary."""
     import torch
     from paper_2310_08710_amd import wm
     dev = device()
@@ -291,14 +326,25 @@ def test_observe_small_and_odd_point_counts():
     ds = wm.upload(sc, dev)
     S, E = sc.num_scenarios, sc.ego.shape[1]
     maxN = ds.batch.max_objects
+
+    def shifted(t):
+        # the same values at an address 4 bytes past a 16-byte boundary
+        buf = torch.empty(t.numel() + 16, dtype=t.dtype, device=dev)
+        off = 4 // t.element_size()
+        buf[off:off + t.numel()] = t
+        return buf[off:off + t.numel()]
+
+    rg_odd = wm.Roadgraph(*(shifted(getattr(ds.rg, f)) for f in ("x", "y", "dir_x", "dir_y", "type", "valid")))
+    assert rg_odd.x.data_ptr() % 16 == 4
     for k in (4, 1000):
-        idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
-        rf = torch.empty((S * E * k * 4,), device=dev)
-        wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, k, idx, rf, None)
-        torch.cuda.synchronize()
         o_idx, o_rf, _ = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, maxN)
-        np.testing.assert_array_equal(idx.cpu().numpy().reshape(S, E, k), o_idx, err_msg="k=%d" % k)
-        assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all(), k
+        for rg in (ds.rg, rg_odd):
+            idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
+            rf = torch.empty((S * E * k * 4,), device=dev)
+            wm.observe(ds.batch, ds.init, rg, ds.ego, E, k, idx, rf, None)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(idx.cpu().numpy().reshape(S, E, k), o_idx, err_msg="k=%d" % k)
+            assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all(), k
 
 
 def test_observe_every_step_of_a_sequence():
