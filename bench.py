@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune", type=str, default=None, help="unit_objects,edge_splits (skips the autotuner)")
     ap.add_argument("--cpu-sample", type=int, default=8, help="scenarios of the oracle sample")
+    ap.add_argument("--observe-only", action="store_true",
+                    help="only time the observation of config 1 (one row, then the 80 logged rows) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device once (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -150,6 +152,11 @@ def main():
     ea = torch.empty((T, n), device=dev)
     ek = torch.empty((T, n), device=dev)
     expert = wm.Action(ea, ek, ds.act_seq.controlled)
+    if args.observe_only:
+        obs = {"workload": "default observation of config 1: 8 egos per scenario, k = 1000, logged rows 1..80"}
+        observation(obs, scene, ds, dev, nxt)
+        print(json.dumps(obs), flush=True)
+        return
     traj = wm.State.empty((T, n), dev)
     met = wm.Metrics.empty((T, n), dev)
     ws = ds.batch.workspace(T, 10)
@@ -236,6 +243,61 @@ def main():
                                          "one scenario per thread (%.1f s wall)" % (args.cpu_sample, secs)}
         log("cpu oracle: %.3e agent-steps/s on %d threads (%.1f s)" % (rate, threads, secs))
     print(json.dumps(out), flush=True)
+
+
+def observation(out, scene, ds, dev, rows_state, reps=3):
+    """Time the default observation of config 1 (8 egos per scenario, k =
+    1000): one state row, then every row of `rows_state` (T rows) in one
+    launch.  Besides the output rate, `point_reads_TBps` is the rate at which
+    the kernel reads road points (x, y, valid: 9 B) from cache, once per ego
+    and row."""
+    import torch
+    from paper_2310_08710_amd import wm
+    S, T = scene.num_scenarios, scene.steps
+    E, K = 8, 1000
+    point_bytes = 9.0 * float(np.sum(np.diff(scene.rg_off))) * E
+    idx = torch.empty(S * E * K, dtype=torch.int32, device=dev)
+    rf = torch.empty(S * E * K * 4, device=dev)
+    of = torch.empty(S * E * ds.batch.max_objects * 8, device=dev)
+    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_OBSERVE)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    oms = 1e3 * (time.perf_counter() - t0) / reps
+    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
+    wm.profile_enable(False)
+    out_bytes = S * E * (K * 20 + ds.batch.max_objects * 32)
+    okm = kms / max(kl, 1)
+    out["observe"] = {"egos_per_s": S * E / (oms * 1e-3), "ms": oms, "kernel_ms": okm, "k": K, "egos": S * E,
+                      "output_GBps": out_bytes / (okm * 1e-3) / 1e9,
+                      "point_reads_TBps": point_bytes / (okm * 1e-3) / 1e12}
+    log("observe: %.3f ms for %d egos (kernel %.3f ms)" % (oms, S * E, okm))
+
+    # every row of a trajectory in one launch
+    del idx, rf, of
+    idx = torch.empty((T, S * E * K), dtype=torch.int32, device=dev)
+    rf = torch.empty((T, S * E * K * 4), device=dev)
+    of = torch.empty((T, S * E * ds.batch.max_objects * 8), device=dev)
+    wm.observe_seq(ds.batch, rows_state, T, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_OBSERVE)
+    t0 = time.perf_counter()
+    wm.observe_seq(ds.batch, rows_state, T, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    sms = 1e3 * (time.perf_counter() - t0)
+    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
+    wm.profile_enable(False)
+    skm = kms / max(kl, 1)
+    out["observe_seq"] = {"ms": sms, "kernel_ms": skm, "rows": T, "egos_per_row": S * E, "k": K,
+                          "ego_steps_per_s": T * S * E / (sms * 1e-3),
+                          "output_GBps": T * out_bytes / (skm * 1e-3) / 1e9,
+                          "point_reads_TBps": T * point_bytes / (skm * 1e-3) / 1e12}
+    log("observe_seq: %.3f ms for %d steps x %d egos" % (sms, T, S * E))
 
 
 def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
@@ -342,48 +404,7 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
                       "checkpoint_every": 10}
     log("fwd+bwd: %.3f ms/rollout (adjoint kernel %.3f ms)" % (fbms, bms / max(bl, 1)))
 
-    # observation: 8 egos per scenario, k = 1000 nearest road points
-    E, K = 8, 1000
-    idx = torch.empty(S * E * K, dtype=torch.int32, device=dev)
-    rf = torch.empty(S * E * K * 4, device=dev)
-    of = torch.empty(S * E * ds.batch.max_objects * 8, device=dev)
-    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
-    torch.cuda.synchronize()
-    wm.profile_enable(True)
-    wm.profile_collect(wm.PROF_OBSERVE)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
-    torch.cuda.synchronize()
-    oms = 1e3 * (time.perf_counter() - t0) / reps
-    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
-    wm.profile_enable(False)
-    out_bytes = S * E * (K * 20 + ds.batch.max_objects * 32)
-    okm = kms / max(kl, 1)
-    out["observe"] = {"egos_per_s": S * E / (oms * 1e-3), "ms": oms, "kernel_ms": okm, "k": K, "egos": S * E,
-                      "output_GBps": out_bytes / (okm * 1e-3) / 1e9}
-    log("observe: %.3f ms for %d egos (kernel %.3f ms)" % (oms, S * E, okm))
-
-    # the observation of every step of the fused rollout's trajectory, one launch
-    del idx, rf, of
-    idx = torch.empty((T, S * E * K), dtype=torch.int32, device=dev)
-    rf = torch.empty((T, S * E * K * 4), device=dev)
-    of = torch.empty((T, S * E * ds.batch.max_objects * 8), device=dev)
-    wm.observe_seq(ds.batch, traj2, T, ds.rg, ds.ego, E, K, idx, rf, of)
-    torch.cuda.synchronize()
-    wm.profile_enable(True)
-    wm.profile_collect(wm.PROF_OBSERVE)
-    t0 = time.perf_counter()
-    wm.observe_seq(ds.batch, traj2, T, ds.rg, ds.ego, E, K, idx, rf, of)
-    torch.cuda.synchronize()
-    sms = 1e3 * (time.perf_counter() - t0)
-    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
-    wm.profile_enable(False)
-    out["observe_seq"] = {"ms": sms, "kernel_ms": kms / max(kl, 1), "rows": T, "egos_per_row": S * E, "k": K,
-                          "ego_steps_per_s": T * S * E / (sms * 1e-3),
-                          "output_GBps": T * out_bytes / (kms / max(kl, 1) * 1e-3) / 1e9}
-    log("observe_seq: %.3f ms for %d steps x %d egos" % (sms, T, S * E))
-    del idx, rf, of
+    observation(out, scene, ds, dev, traj2, reps)
 
     ragged(out, dev)
     idm(out, scene, ds, dev, tune)

@@ -2,26 +2,30 @@
 // and the k road points nearest to the ego, exact, ascending by
 // (binary32 squared distance, index).
 //
-// One 1024-thread work-group per (row, scenario, ego); two fit on a CU.  Each
-// thread keeps up to 32 keys in registers (points j = tid + 1024 r), so a
-// scenario's road graph is read once per ego.  The keys are non-negative
-// floats, whose bit patterns order like their values.
+// One 1024-thread work-group per (row, scenario, ego); two fit on a CU.  A
+// scenario's road graph is read once per ego (point j by thread j % 1024).
+// The keys are non-negative floats, whose bit patterns order like their
+// values.
 //   1. Every 16th point is sampled; a histogram of the samples' top bits
 //      (exponent and three mantissa bits) gives a bound U below which about
-//      1.5 k keys should lie.  The keys below U are appended to an LDS list
-//      (one atomic per wave).  If the list holds at least k keys and did not
-//      overflow, the rest are never touched again; otherwise (rarely) every
-//      point is a candidate, its key recomputed from the road graph.
-//   2. A histogram of the candidates' first digit (key bits 19..30: exponent
+//      1.5 k keys should lie.
+//   2. Every key is computed once; those below U are appended to an LDS list
+//      (wave ballots, one atomic per wave and round that has any).  If the
+//      list holds at least k keys and did not overflow, the rest are never
+//      touched again; otherwise (rarely) every point is a candidate, its key
+//      recomputed from the road graph.
+//   3. A histogram of the candidates' first digit (key bits 19..30: exponent
 //      and four mantissa bits, 4096 bins) locates the bin b holding the k-th
 //      key; every candidate below that bin is selected.
-//   3. The keys of bin b (rarely more than a few hundred; otherwise the next
+//   4. The keys of bin b (rarely more than a few hundred; otherwise the next
 //      digits narrow it first) are ranked among themselves by (key, index),
 //      and the lowest ones fill the last places.
-//   4. The selected keys below bin b are scattered into LDS grouped by their
+//   5. The selected keys below bin b are scattered into LDS grouped by their
 //      bin, whose output range is known from the histogram's prefix sum, and
 //      each one's place is the start of its bin plus the number of keys of
 //      that bin that precede it.
+//   6. The places are collected in LDS and the outputs written in place
+//      order (coalesced).
 // No sorting network: nine work-group barriers per ego on the list path.
 #include "wm_device.h"
 #include "wm_internal.h"
@@ -40,6 +44,7 @@ constexpr int kSampleBins = 2048;                               // sample digit:
 constexpr int kSampleShift = 20;
 constexpr int kCandCap = 1024;                                  // boundary keys ranked directly
 constexpr int kListCap = 3072;                                  // candidates compacted into LDS
+static_assert(kListCap >= WM_MAX_TOPK, "the list's key array then holds the output order");
 
 __device__ __forceinline__ uint32_t topk_key(float qx, float qy, float ex, float ey)
 {
@@ -98,28 +103,6 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-struct ObsOut {
-    int32_t *idx;
-    float *feat;
-    const float *x, *y, *dx, *dy;
-    float ex, ey, es, ec;
-};
-
-// Output place `pos` of this ego receives the scenario's road point `j`
-// (h: its position in the packed arrays).
-__device__ __forceinline__ void emit(const ObsOut &o, long pos, int j, int h)
-{
-    o.idx[pos] = j;
-    if (o.feat) {
-        const float dx = o.x[h] - o.ex, dy = o.y[h] - o.ey;
-        float *f = o.feat + 4 * pos;
-        f[0] = __builtin_fmaf(o.ec, dx, o.es * dy);
-        f[1] = __builtin_fmaf(o.ec, dy, -(o.es * dx));
-        f[2] = __builtin_fmaf(o.ec, o.dx[h], o.es * o.dy[h]);
-        f[3] = __builtin_fmaf(o.ec, o.dy[h], -(o.es * o.dx[h]));
-    }
-}
-
 struct TopkLds {
     int *hist;           // [kHistCopies][kBins] digit histograms; copy 0 then the scatter cursors
     int *base;           // [kBins + 1] exclusive prefix of the first-digit histogram
@@ -127,6 +110,7 @@ struct TopkLds {
     uint64_t *cand;      // [kCandCap] keys of the boundary set
     uint32_t *wtot;      // [16] per-wave totals of block_exclusive
     int *sh;             // [4] bin, before, count, boundary-list length
+    int *order;          // [WM_MAX_TOPK] the point at each output place
 };
 
 // Every point of the scenario as a candidate, its key recomputed from the
@@ -164,15 +148,14 @@ struct ListKeys {
     }
 };
 
-// Selects and writes the kk (>= 1, <= number of candidates) smallest
-// candidates in (key, index) order; every candidate not given is larger than
-// every one given.  Returns false, having written nothing, when the boundary
+// Selects the kk (>= 1, <= number of candidates) smallest candidates in
+// (key, index) order into L.order[0, kk); every candidate not given is larger
+// than every one given.  Returns false, having written nothing, when the boundary
 // set is over kCandCap equal keys and the candidates are not AllKeys (whose
 // fixed index order that case needs).  Work-group-wide; every thread calls it
 // with the same arguments.
 template <bool kReg, class Src>
-__device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLds &L, const ObsOut &o, int p0,
-                                            bool cleared)
+__device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLds &L, bool cleared)
 {
     const int tid = threadIdx.x;
     if (!cleared) {
@@ -293,10 +276,8 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
         for (int c = kObsThreads - 1 - tid; c < nB; c += kObsThreads) {
             const uint64_t own = L.cand[c];
             const int before = count_below(L.cand, 0, nB, own);
-            if (before < need) {
-                const int j = (int)(uint32_t)own;
-                emit(o, c_less + before, j, p0 + j);
-            }
+            if (before < need)
+                L.order[c_less + before] = (int)(uint32_t)own;
         }
     } else if (kReg) {
         // every key of the boundary set is equal (all digits fixed): the
@@ -321,10 +302,8 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
             }
             if ((eqm >> r) & 1u) {
                 const int rk = rounds_before + waves_before + __popcll(bal & ((1ull << lane) - 1ull));
-                if (rk < need) {
-                    const int j = tid + kObsThreads * r;
-                    emit(o, c_less + rk, j, p0 + j);
-                }
+                if (rk < need)
+                    L.order[c_less + rk] = tid + kObsThreads * r;
             }
             rounds_before += round_tot;
         }
@@ -334,8 +313,7 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
         const uint64_t own = L.sel[i];
         const int d = (int)(own >> (32 + kDigitShift));
         const int start = L.base[d], end = d == b1 ? c_less : L.base[d + 1];
-        const int j = (int)(uint32_t)own;
-        emit(o, start + count_below(L.sel, start, end, own), j, p0 + j);
+        L.order[start + count_below(L.sel, start, end, own)] = (int)(uint32_t)own;
     }
     return true;
 }
@@ -366,7 +344,7 @@ __global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))
     __shared__ uint32_t wtot[kObsThreads / 64];
     __shared__ int sh[4];
     __shared__ uint32_t sh_bound, sh_nvalid, sh_nU;
-    const TopkLds L{hist, base, sel, cand, wtot, sh};
+    const TopkLds L{hist, base, sel, cand, wtot, sh, (int *)lkey};   // the list is done with when places are set
     const int tid = threadIdx.x;
     const int o0 = A.obj_off[s], N = A.obj_off[s + 1] - o0;
     const int p0 = A.rg_off[s], P = A.rg_off[s + 1] - p0;
@@ -409,98 +387,106 @@ __global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))
         }
     }
 
-    // ---- keys ----
-    uint32_t key[kObsKeys];
+    // ---- pass A: the sample (every 16th point) bounds the k-th key ----
+    const float *rx = A.rg.x + p0, *ry = A.rg.y + p0;
+    const uint8_t *rv = A.rg.valid + p0;
+    const bool have = ego_valid && P > 0;
+    if (have) {
 #pragma unroll
-    for (int r = 0; r < kObsKeys; ++r)
-        key[r] = kNoKey;
-    if (ego_valid && P > 0) {
-        // indices past the scenario's points are clamped to its last point
-        // (an in-bounds load) and give no key
-        const float *rx = A.rg.x + p0, *ry = A.rg.y + p0;
-        const uint8_t *rv = A.rg.valid + p0;
-#pragma unroll
-        for (int r = 0; r < kObsKeys; ++r) {
-            const int j = tid + kObsThreads * r, jj = min(j, P - 1);
-            const float qx = rx[jj], qy = ry[jj];
-            const bool v = rv[jj] != 0;
-            const uint32_t kq = topk_key(qx, qy, ex, ey);
-            key[r] = (j < P && v) ? kq : kNoKey;
+        for (int h = 0; h < 2; ++h) {   // 16 (tid + 1024 h) covers every multiple of 16 below 32768
+            const int j = 16 * (tid + kObsThreads * h);
+            if (j < P && rv[j])
+                atomicAdd(&hs[topk_key(rx[j], ry[j], ex, ey) >> kSampleShift], 1);
         }
     }
-    __syncthreads();   // hs cleared
-
-    // ---- sample (every 16th point): valid count and the bound U ----
-    int nv_local = 0;
-#pragma unroll
-    for (int r = 0; r < kObsKeys; ++r) {
-        nv_local += key[r] != kNoKey;
-        if ((tid & 15) == 0 && key[r] != kNoKey)
-            atomicAdd(&hs[key[r] >> kSampleShift], 1);
-    }
-    const uint32_t nv_wave = wave_sum((uint32_t)nv_local);
-    if ((tid & 63) == 0)
-        atomicAdd(&sh_nvalid, nv_wave);
     __syncthreads();
-    const int nvalid = __builtin_amdgcn_readfirstlane(sh_nvalid);
-    const int kk = min(A.k, nvalid);
     const int s0 = hs[2 * tid], s1 = hs[2 * tid + 1];
     uint32_t ns;
     const int exs = (int)block_exclusive((uint32_t)(s0 + s1), wtot, &ns);
-    const int want = (3 * kk + 31) / 32 + 4;   // samples below U: 1.5 kk / 16, plus slack
+    // the ns samples stand for about 16 ns valid points: aim at 1.5 k' keys
+    // below U, k' = min(k, 16 ns)
+    const int k_est = min(A.k, 16 * (int)ns);
+    const int want = (3 * k_est + 31) / 32 + 4;
     if (want < (int)ns && exs <= want - 1 && want - 1 < exs + s0 + s1)
         sh_bound = (uint32_t)(want - 1 < exs + s0 ? 2 * tid + 1 : 2 * tid + 2) << kSampleShift;
     __syncthreads();
     const uint32_t U = __builtin_amdgcn_readfirstlane(sh_bound);
 
-    // ---- the keys below U, appended to the list (any order: the
-    // selection ranks by (key, index)); one list atomic per wave ----
-    if (kk > 0) {
-        int below = 0;
-#pragma unroll
-        for (int r = 0; r < kObsKeys; ++r)
-            below += key[r] < U;   // kNoKey is never below U
-        const int lane = tid & 63;
-        int incl = below;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int u = __shfl_up(incl, d);
-            if (lane >= d)
-                incl += u;
-        }
-        int wbase = 0;
-        if (lane == 63)
-            wbase = (int)atomicAdd(&sh_nU, (uint32_t)incl);
-        int off = __shfl(wbase, 63) + incl - below;
-#pragma unroll
-        for (int r = 0; r < kObsKeys; ++r)
-            if (key[r] < U) {
-                if (off < kListCap) {
-                    lkey[off] = key[r];
-                    lidx[off] = (uint32_t)(tid + kObsThreads * r);
+    // ---- pass B: every key, once; those below U are appended to the list
+    // (any order: the selection ranks by (key, index)), one list atomic per
+    // wave and round that has any ----
+    const int lane = tid & 63;
+    int nv_local = 0;
+    if (have) {
+#pragma unroll 8
+        for (int r = 0; r < kObsKeys; ++r) {
+            if (kObsThreads * r >= P)   // block-uniform
+                break;
+            // indices past the scenario's points are clamped to its last
+            // point (an in-bounds load) and give no key
+            const int j = tid + kObsThreads * r, jj = min(j, P - 1);
+            const uint32_t kq = topk_key(rx[jj], ry[jj], ex, ey);
+            const bool v = j < P && rv[jj] != 0;
+            nv_local += v;
+            const bool in = v && kq < U;
+            const uint64_t bal = __ballot(in);
+            if (bal) {   // wave-uniform
+                int base = 0;
+                if (lane == 0)
+                    base = (int)atomicAdd(&sh_nU, (uint32_t)__popcll(bal));
+                const int at = __builtin_amdgcn_readfirstlane(base) + __popcll(bal & ((1ull << lane) - 1ull));
+                if (in && at < kListCap) {
+                    lkey[at] = kq;
+                    lidx[at] = (uint32_t)j;
                 }
-                ++off;
             }
+        }
     }
+    const uint32_t nv_wave = wave_sum((uint32_t)nv_local);
+    if (lane == 0)
+        atomicAdd(&sh_nvalid, nv_wave);
     __syncthreads();
+    const int nvalid = __builtin_amdgcn_readfirstlane(sh_nvalid);
+    const int kk = min(A.k, nvalid);
     const int nU = __builtin_amdgcn_readfirstlane((int)sh_nU);
 
-    ObsOut o{A.rg_idx + (orow + slot) * A.k, A.rg_feat ? A.rg_feat + (orow + slot) * A.k * 4 : nullptr,
-             A.rg.x, A.rg.y, A.rg.dir_x, A.rg.dir_y, ex, ey, es, ec};
     // the list holds the nU smallest keys; it serves when that is at least
     // kk and fits (otherwise, rarely: the sample misled, or too many keys
     // share the bound's bin), every point is a candidate
     bool done = kk == 0;
     if (!done && nU >= kk && nU <= kListCap)
-        done = topk_select<false>(ListKeys{lkey, lidx, nU}, kk, L, o, p0, true);
+        done = topk_select<false>(ListKeys{lkey, lidx, nU}, kk, L, true);
     if (!done)
         topk_select<true>(AllKeys{A.rg.x + p0, A.rg.y + p0, A.rg.valid + p0, P, ego_valid && P > 0, ex, ey}, kk,
-                          L, o, p0, false);
-    // ---- padding ----
-    for (int r = kk + tid; r < A.k; r += kObsThreads) {
-        o.idx[r] = -1;
-        if (o.feat)
-            for (int c = 0; c < 4; ++c)
-                o.feat[4L * r + c] = 0.f;
+                          L, false);
+    __syncthreads();
+
+    // ---- outputs in place order (coalesced), then the padding ----
+    const long out0 = (orow + slot) * (long)A.k;
+    float *feat = A.rg_feat ? A.rg_feat + 4 * out0 : nullptr;
+    const bool feat16 = ((uintptr_t)A.rg_feat & 15u) == 0;
+    for (int r = tid; r < A.k; r += kObsThreads) {
+        const int j = r < kk ? L.order[r] : -1;
+        A.rg_idx[out0 + r] = j;
+        if (feat) {
+            float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j >= 0) {
+                const int h = p0 + j;
+                const float dx = A.rg.x[h] - ex, dy = A.rg.y[h] - ey;
+                f.x = __builtin_fmaf(ec, dx, es * dy);
+                f.y = __builtin_fmaf(ec, dy, -(es * dx));
+                f.z = __builtin_fmaf(ec, A.rg.dir_x[h], es * A.rg.dir_y[h]);
+                f.w = __builtin_fmaf(ec, A.rg.dir_y[h], -(es * A.rg.dir_x[h]));
+            }
+            if (feat16) {
+                *(float4 *)(feat + 4L * r) = f;
+            } else {
+                feat[4L * r] = f.x;
+                feat[4L * r + 1] = f.y;
+                feat[4L * r + 2] = f.z;
+                feat[4L * r + 3] = f.w;
+            }
+        }
     }
 }
 
