@@ -26,7 +26,7 @@
 //      that bin that precede it.
 //   6. The places are collected in LDS and the outputs written in place
 //      order (coalesced).
-// No sorting network: nine work-group barriers per ego on the list path.
+// No sorting network: twelve work-group barriers per ego on the list path.
 #include "wm_device.h"
 #include "wm_internal.h"
 
@@ -391,6 +391,7 @@ __global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))
     const float *rx = A.rg.x + p0, *ry = A.rg.y + p0;
     const uint8_t *rv = A.rg.valid + p0;
     const bool have = ego_valid && P > 0;
+    __syncthreads();   // hs, hist and the counters are cleared
     if (have) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {   // 16 (tid + 1024 h) covers every multiple of 16 below 32768
