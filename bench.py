@@ -56,21 +56,29 @@ def rollout_ops(scene, T):
     return per_step * T, float((4.0 * N * E).sum() * T)
 
 
+# The sources k_rollout is compiled from: its counters stay valid while these
+# and the tuning are unchanged.
+ROLLOUT_SOURCES = ("paper_2310_08710_amd/csrc/wm_kernels.hip", "paper_2310_08710_amd/csrc/wm_device.h",
+                   "paper_2310_08710_amd/csrc/wm_internal.h", "include/wm.h")
+
+
+def rollout_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ROLLOUT_SOURCES:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def recorded_traffic(tune):
     """HBM-side bytes per k_rollout launch from the committed rocprofv3
-    counter runs, or None when the device sources (*.hip, *.h) or the tuning
-    changed since."""
-    import glob
-    import hashlib
+    counter runs, or None when k_rollout's sources or the tuning changed
+    since."""
     path = os.path.join(ROOT, "profiles", "k_rollout_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2310_08710_amd", "csrc")
-    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(open(p, "rb").read())
-    if rec.get("sources_sha256") != h.hexdigest() or list(rec.get("tuning", [])) != list(tune or []):
+    if rec.get("sources_sha256") != rollout_sources_sha256() or list(rec.get("tuning", [])) != list(tune or []):
         return None
     return float(rec["traffic_bytes_per_launch"])
 
