@@ -625,6 +625,7 @@ int wm_rollout_backward(const wm_batch *batch, const wm_state *init, const wm_ac
     a.T = T;
     a.K = ckpt_every;
     a.maxN = batch->max_objects;
+    a.SB = wm::backward_block_steps(a.maxN, a.K);
     a.dt = dt;
     a.obj_off = batch->obj_off;
     a.init = *init;

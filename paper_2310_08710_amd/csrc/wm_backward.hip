@@ -2,16 +2,25 @@
 // loss with respect to the actions (differentiable simulation, Sec. 1 and
 // Sec. 6; dynamics of App. A.1).
 //
-// One work-group per scenario.  The forward pass stored the state every K
-// steps; each segment [cK, min(cK + K, T)] is recomputed from its checkpoint
-// with the same device code as the forward (bit-identical states), written to
-// the workspace, and swept in reverse:
-//   1. loss adjoint at step t: 2 (p - p_log) for controlled objects, plus
-//      sigmoid'(m / 0.1) / 0.1 * dm/d(x, y, yaw) for every pair with a
-//      controlled member (each controlled object gathers its own side of
-//      every pair, split over threads and summed in a fixed order);
-//   2. back through the bicycle step t: gradients of (a, kappa) at t-1 and
-//      the adjoint of the previous state.
+// One 1024-thread work-group per scenario.  The forward pass stored the state
+// every K steps; each segment [cK, min(cK + K, T)] is recomputed from its
+// checkpoint with the same device code as the forward (bit-identical states)
+// into the workspace and swept in reverse, SB steps at a time:
+//   1. every object's state at those SB steps goes to LDS (controlled ones
+//      from the recomputation, the others from the log);
+//   2. the loss gradient with respect to each controlled object's (x, y,
+//      yaw) at each of those steps: sigmoid'(m / 0.1) / 0.1 * dm/d(x, y, yaw)
+//      over every pair with a controlled member.  The pair terms do not
+//      depend on the adjoint, so all SB steps are done at once: a group of
+//      G lanes per (step, controlled object) splits the partners (j = lane,
+//      lane + G, ...) and sums them with a fixed shuffle tree;
+//   3. one thread per controlled object runs the reverse recursion over the
+//      SB steps: the log-divergence term 2 (p - p_log), then back through the
+//      bicycle step, with the object's adjoint held in registers and its
+//      inputs (log position, previous state, action), which do not depend on
+//      the adjoint, staged in LDS with the states.
+// G depends only on the scenario's object count and SB only changes the
+// blocking, so the gradients are identical for every checkpoint interval.
 // Only controlled, valid objects carry adjoints: replayed objects do not
 // depend on the actions and frozen objects never enter the loss.
 #include "wm_device.h"
@@ -19,33 +28,75 @@
 
 namespace wm {
 
-constexpr int kBwdThreads = 256;
+constexpr int kBwdThreads = 1024;
+constexpr size_t kBwdStageBudget = 96 * 1024;   // LDS for the SB-step blocks
+constexpr int kBwdRec = 8;                       // recursion inputs per (step, controlled object)
+constexpr size_t kBwdStepBytes = 16 + 8 + 3 * 4 + kBwdRec * 4;   // LDS per step and object
+
+// Margin of the separating-axis test (the same value as sat_margin) and its
+// gradient with respect to (x, y, yaw) of box a (of_b false) or box b (of_b
+// true), through the arg-min axis (lowest axis index on ties), sgn(0) = +1,
+// as sat_margin_grad.
+__device__ __forceinline__ float sat_margin_grad_one(const Box &a, const Box &b, bool of_b, float &gx, float &gy,
+                                                     float &gt)
+{
+    const float dx = b.x - a.x, dy = b.y - a.y;
+    const float cd = __builtin_fmaf(a.c, b.c, a.s * b.s);    // cos(delta), delta = yaw_b - yaw_a
+    const float sd = __builtin_fmaf(a.c, b.s, -(a.s * b.c)); // sin(delta)
+    const float C = fabsf(cd), S = fabsf(sd);
+    const float dC = -(cd >= 0.f ? 1.f : -1.f) * sd;
+    const float dS = (sd >= 0.f ? 1.f : -1.f) * cd;
+    const float pua = __builtin_fmaf(dx, a.c, dy * a.s), pwa = __builtin_fmaf(dy, a.c, -(dx * a.s));
+    const float pub = __builtin_fmaf(dx, b.c, dy * b.s), pwb = __builtin_fmaf(dy, b.c, -(dx * b.s));
+    const float g0 = a.hl + __builtin_fmaf(b.hl, C, b.hw * S) - fabsf(pua);
+    const float g1 = a.hw + __builtin_fmaf(b.hl, S, b.hw * C) - fabsf(pwa);
+    const float g2 = b.hl + __builtin_fmaf(a.hl, C, a.hw * S) - fabsf(pub);
+    const float g3 = b.hw + __builtin_fmaf(a.hl, S, a.hw * C) - fabsf(pwb);
+    // arg-min with selects (lowest index on ties)
+    const bool k1 = g1 < g0;
+    float m = k1 ? g1 : g0;
+    const bool k2 = g2 < m;
+    m = k2 ? g2 : m;
+    const bool k3 = g3 < m;
+    m = k3 ? g3 : m;
+    const int k = k3 ? 3 : (k2 ? 2 : (k1 ? 1 : 0));
+    const bool on_a = k < 2, odd = (k & 1) != 0;
+    // axis (ax, ay), projection p of the offset on it, d(radius)/d(delta) rd,
+    // and d(p)/d(own yaw) of the box whose axis it is
+    const float bc = on_a ? a.c : b.c, bs = on_a ? a.s : b.s;
+    const float ax = odd ? -bs : bc, ay = odd ? bc : bs;
+    const float p = on_a ? (odd ? pwa : pua) : (odd ? pwb : pub);
+    const float hl = on_a ? b.hl : a.hl, hw = on_a ? b.hw : a.hw;
+    const float rd = odd ? __builtin_fmaf(hl, dS, hw * dC) : __builtin_fmaf(hl, dC, hw * dS);
+    const float dp = on_a ? (odd ? -pua : pwa) : (odd ? -pub : pwb);
+    const float sp = p >= 0.f ? 1.f : -1.f;
+    if (!of_b) {
+        gx = sp * ax;
+        gy = sp * ay;
+        gt = -rd - (on_a ? sp * dp : 0.f);
+    } else {
+        gx = -sp * ax;
+        gy = -sp * ay;
+        gt = rd - (on_a ? 0.f : sp * dp);
+    }
+    return m;
+}
 
 __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int maxN = A.maxN;
-    ObjLds L;
-    float *f = (float *)smem;
-    L.x = f;
-    L.y = f + maxN;
-    L.yaw = f + 2 * maxN;
-    L.vx = f + 3 * maxN;
-    L.vy = f + 4 * maxN;
-    L.len = f + 5 * maxN;
-    L.wid = f + 6 * maxN;
-    L.c = f + 7 * maxN;
-    L.s = f + 8 * maxN;
-    const int PS = maxN > kBwdThreads ? maxN : kBwdThreads;
-    float *adj = f + 9 * maxN;                   // [5][maxN] adjoints (x, y, yaw, vx, vy)
-    float *part = adj + 5 * maxN;                // [3][PS] pair partials
-    int *cidx = (int *)(part + 3 * PS);          // controlled & valid objects
-    uint8_t *b8 = (uint8_t *)(cidx + maxN);
-    L.valid = b8;
-    L.ctrl = b8 + maxN;
+    const int maxN = A.maxN, SB = A.SB;
+    // LDS: [SB][maxN] (x, y, cos, sin) and (half length or -1 when invalid,
+    // half width); the pair-term sums [SB][maxN][3] and the recursion's
+    // inputs [SB][maxN][8] per controlled slot; the controlled objects' indices
+    float4 *st4 = (float4 *)smem;
+    float2 *st2 = (float2 *)(st4 + SB * maxN);
+    float *part = (float *)(st2 + SB * maxN);
+    float *rec = part + 3 * SB * maxN;
+    int *cidx = (int *)(rec + kBwdRec * SB * maxN);
     __shared__ int s_nc;
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
     const int s = blockIdx.x;
     const int o0 = A.obj_off[s], N = A.obj_off[s + 1] - o0;
     const long n = A.n;
@@ -59,10 +110,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                 cidx[nc++] = i;
         s_nc = nc;
     }
-    for (int i = tid; i < N; i += kBwdThreads) {
-        L.ctrl[i] = A.act.controlled[o0 + i];
-        for (int c = 0; c < 5; ++c)
-            adj[c * maxN + i] = 0.f;
+    for (int i = tid; i < N; i += nthr) {
         const bool live = A.act.controlled[o0 + i] && A.init.valid[o0 + i];
         if (!live)
             for (int t = 0; t < A.T; ++t) {
@@ -72,15 +120,25 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
     }
     __syncthreads();
     const int NC = s_nc;
-    const int P = NC > 0 ? max(1, kBwdThreads / NC) : 1;
+    // partner split: G lanes (a power of two <= 64) per (step, controlled
+    // object), about 16 partners each
+    int G = 1;
+    while (G < 64 && G * 16 < N)
+        G <<= 1;
     const int nseg = (A.T + A.K - 1) / A.K;
     float *seg = A.seg;
+    // the adjoint of this thread's controlled object (x, y, yaw, vx, vy)
+    float bx = 0.f, by = 0.f, byaw = 0.f, bvx = 0.f, bvy = 0.f;
+    const int q = tid;
+    const int i_own = q < NC ? cidx[q] : 0;
+    const long g_own = o0 + i_own;
 
     for (int c = nseg - 1; c >= 0; --c) {
         const int t0 = c * A.K, t1 = min(A.T, t0 + A.K);
+        __syncthreads();   // the previous block's readers of seg are done
         // recompute the controlled objects' states t0..t1 into the workspace
-        for (int q = tid; q < NC; q += kBwdThreads) {
-            const long g = o0 + cidx[q];
+        for (int qq = tid; qq < NC; qq += nthr) {
+            const long g = o0 + cidx[qq];
             float x = A.ckpt.x[(long)c * n + g], y = A.ckpt.y[(long)c * n + g], yaw = A.ckpt.yaw[(long)c * n + g];
             float vx = A.ckpt.vx[(long)c * n + g], vy = A.ckpt.vy[(long)c * n + g];
             for (int t = t0; t <= t1; ++t) {
@@ -96,15 +154,18 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
             }
         }
         __syncthreads();
-        for (int t = t1; t > t0; --t) {
-            const float *row = seg + (long)(t - t0) * 5 * n;
-            const long lrow = (long)t * n;
-            // state at t: controlled from the recomputation, others from the log
-            for (int i = tid; i < N; i += kBwdThreads) {
-                const long g = o0 + i;
+        // blocks of SB steps, last block first: steps tb_lo + 1 .. tb_hi
+        for (int tb_hi = t1; tb_hi > t0; tb_hi -= SB) {
+            const int tb_lo = max(t0, tb_hi - SB), nb = tb_hi - tb_lo;
+            // 1. states of every object at steps tb_lo + 1 .. tb_hi (slot tb = t - tb_lo - 1)
+            for (int it = tid; it < nb * N; it += nthr) {
+                const int tb = it / N, i = it - tb * N;
+                const int t = tb_lo + 1 + tb;
+                const float *row = seg + (long)(t - t0) * 5 * n;
+                const long g = o0 + i, lrow = (long)t * n;
                 float x, y, yaw, len, wid;
                 uint8_t v;
-                if (L.ctrl[i]) {
+                if (A.act.controlled[g]) {
                     v = A.init.valid[g];
                     len = A.init.length[g];
                     wid = A.init.width[g];
@@ -125,108 +186,158 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                     len = A.log.length[lrow + g];
                     wid = A.log.width[lrow + g];
                 }
-                L.x[i] = x;
-                L.y[i] = y;
-                L.yaw[i] = yaw;
-                L.len[i] = len;
-                L.wid[i] = wid;
-                L.valid[i] = v;
                 float sn, cs;
                 sincosf(yaw, &sn, &cs);
-                L.c[i] = cs;
-                L.s[i] = sn;
+                const int at = tb * maxN + i;
+                st4[at] = make_float4(x, y, cs, sn);
+                st2[at] = make_float2(v ? 0.5f * len : -1.f, 0.5f * wid);
             }
-            __syncthreads();
-            // pair partials: work item (q = controlled slot, p = partner split)
-            for (int wi = tid; wi < NC * P; wi += kBwdThreads) {
-                const int q = wi % NC, p = wi / NC;
-                const int i = cidx[q];
-                float gx = 0.f, gy = 0.f, gt = 0.f;
-                Box bi;
-                bi.x = L.x[i]; bi.y = L.y[i]; bi.c = L.c[i]; bi.s = L.s[i];
-                bi.hl = 0.5f * L.len[i]; bi.hw = 0.5f * L.wid[i];
-                for (int j = p; j < N; j += P) {
-                    if (j == i || !L.valid[j])
-                        continue;
-                    Box bj;
-                    bj.x = L.x[j]; bj.y = L.y[j]; bj.c = L.c[j]; bj.s = L.s[j];
-                    bj.hl = 0.5f * L.len[j]; bj.hw = 0.5f * L.wid[j];
-                    float ga[3], gb[3], m;
-                    if (i < j) {
-                        m = sat_margin(bi, bj);
-                        sat_margin_grad(bi, bj, ga, gb);
-                    } else {
-                        m = sat_margin(bj, bi);
-                        sat_margin_grad(bj, bi, gb, ga);
-                    }
-                    const float sg = 1.0f / (1.0f + expf(-m * (1.0f / kSoftScale)));
-                    const float dm = sg * (1.0f - sg) * (1.0f / kSoftScale);
-                    gx = __builtin_fmaf(dm, ga[0], gx);
-                    gy = __builtin_fmaf(dm, ga[1], gy);
-                    gt = __builtin_fmaf(dm, ga[2], gt);
-                }
-                part[wi] = gx;
-                part[PS + wi] = gy;
-                part[2 * PS + wi] = gt;
-            }
-            __syncthreads();
-            // per controlled object: add the loss adjoint, then step back through t
-            for (int q = tid; q < NC; q += kBwdThreads) {
-                const int i = cidx[q];
-                const long g = o0 + i;
-                float px = 0.f, py = 0.f, pt = 0.f;
-                for (int p = 0; p < P; ++p) {
-                    px += part[p * NC + q];
-                    py += part[PS + p * NC + q];
-                    pt += part[2 * PS + p * NC + q];
-                }
-                float bx = adj[i] + w * px, by = adj[maxN + i] + w * py, byaw = adj[2 * maxN + i] + w * pt;
-                const float bvx = adj[3 * maxN + i], bvy = adj[4 * maxN + i];
-                if (A.log.valid[lrow + g]) {
-                    bx += w * 2.f * (L.x[i] - A.log.x[lrow + g]);
-                    by += w * 2.f * (L.y[i] - A.log.y[lrow + g]);
-                }
-                // previous state (t - 1) and the action of step t
+            // the recursion's inputs, which do not depend on the adjoint: the
+            // log position at t, the state at t - 1 and the action of step t
+            for (int it = tid; it < nb * NC; it += nthr) {
+                const int tb = it / NC, qq = it - tb * NC;
+                const int t = tb_lo + 1 + tb;
+                const long g = o0 + cidx[qq], lrow = (long)t * n;
                 const float *prow = seg + (long)(t - 1 - t0) * 5 * n;
-                const float yaw0 = prow[2 * n + g], vx0 = prow[3 * n + g], vy0 = prow[4 * n + g];
-                const float a = A.act.accel[(long)(t - 1) * n + g], k = A.act.curvature[(long)(t - 1) * n + g];
-                const float v = sqrtf(__builtin_fmaf(vy0, vy0, vx0 * vx0));
-                const float dist = __builtin_fmaf(v, dt, a * hdt2);
-                const float nv = __builtin_fmaf(a, dt, v);
-                const float nyaw = L.yaw[i];
-                float ns, nc;
-                sincosf(nyaw, &ns, &nc);
-                float s0, c0;
-                sincosf(yaw0, &s0, &c0);
-                const float bnv = __builtin_fmaf(bvx, nc, bvy * ns);
-                const float tyaw = byaw + nv * __builtin_fmaf(bvy, nc, -(bvx * ns));
-                const float ga_ = __builtin_fmaf(hdt2, __builtin_fmaf(bx, c0, __builtin_fmaf(by, s0, k * tyaw)), dt * bnv);
-                const float gk_ = dist * tyaw;
-                const float pyaw = tyaw + a * hdt2 * __builtin_fmaf(by, c0, -(bx * s0));
-                const float bv = __builtin_fmaf(k * dt, tyaw, bnv);
-                const float inv = v > 0.f ? bv / v : 0.f;
-                A.grad_a[(long)(t - 1) * n + g] = ga_;
-                A.grad_k[(long)(t - 1) * n + g] = gk_;
-                adj[i] = bx;
-                adj[maxN + i] = by;
-                adj[2 * maxN + i] = pyaw;
-                adj[3 * maxN + i] = __builtin_fmaf(dt, bx, inv * vx0);
-                adj[4 * maxN + i] = __builtin_fmaf(dt, by, inv * vy0);
+                float *r = rec + kBwdRec * (tb * maxN + qq);
+                r[0] = A.log.x[lrow + g];
+                r[1] = A.log.y[lrow + g];
+                r[2] = A.log.valid[lrow + g] ? 1.f : 0.f;
+                r[3] = prow[2 * n + g];
+                r[4] = prow[3 * n + g];
+                r[5] = prow[4 * n + g];
+                r[6] = A.act.accel[(long)(t - 1) * n + g];
+                r[7] = A.act.curvature[(long)(t - 1) * n + g];
             }
             __syncthreads();
+            // 2. pair terms of every (step, controlled object): item u = (tb,
+            // q, lane of the group); the groups never straddle a wave
+            const int items = nb * NC * G;
+            for (int u0 = 0; u0 < items; u0 += nthr) {   // block-uniform trip count
+                const int u = u0 + tid;
+                float gx = 0.f, gy = 0.f, gt = 0.f;
+                const int grp = u / G, gl = u - grp * G;
+                const int tb = grp / max(NC, 1), qq = grp - tb * NC;
+                if (u < items) {
+                    const int i = cidx[qq];
+                    const float4 pi = st4[tb * maxN + i];
+                    const float2 hi = st2[tb * maxN + i];
+                    const Box bi{pi.x, pi.y, pi.z, pi.w, hi.x, hi.y};
+                    const float4 *row4 = st4 + tb * maxN;
+                    const float2 *row2 = st2 + tb * maxN;
+                    // the partners j = gl, gl + G, ... in ascending order, two
+                    // per iteration; a term of j == i or of an invalid j is 0
+                    auto term = [&](int j, float &tx, float &ty, float &tt) {
+                        const float4 pj = row4[j];
+                        const float2 hj = row2[j];
+                        const Box bj{pj.x, pj.y, pj.z, pj.w, hj.x, hj.y};
+                        float ux, uy, ut;
+                        // the pair's margin with the lower index first, as in the forward
+                        const float m = i < j ? sat_margin_grad_one(bi, bj, false, ux, uy, ut)
+                                              : sat_margin_grad_one(bj, bi, true, ux, uy, ut);
+                        const float sg = 1.0f / (1.0f + expf(-m * (1.0f / kSoftScale)));
+                        const float dm = sg * (1.0f - sg) * (1.0f / kSoftScale);
+                        // selects, not products: an invalid object's values may be anything
+                        const bool ok = j != i && hj.x >= 0.f;
+                        tx = ok ? dm * ux : 0.f;
+                        ty = ok ? dm * uy : 0.f;
+                        tt = ok ? dm * ut : 0.f;
+                    };
+                    int j = gl;
+                    for (; j + G < N; j += 2 * G) {
+                        float ax, ay, at, bx2, by2, bt;
+                        term(j, ax, ay, at);
+                        term(j + G, bx2, by2, bt);
+                        gx += ax;
+                        gy += ay;
+                        gt += at;
+                        gx += bx2;
+                        gy += by2;
+                        gt += bt;
+                    }
+                    if (j < N) {
+                        float ax, ay, at;
+                        term(j, ax, ay, at);
+                        gx += ax;
+                        gy += ay;
+                        gt += at;
+                    }
+                }
+                for (int d = G >> 1; d > 0; d >>= 1) {   // fixed tree within the group
+                    gx += __shfl_xor(gx, d);
+                    gy += __shfl_xor(gy, d);
+                    gt += __shfl_xor(gt, d);
+                }
+                if (u < items && gl == 0) {
+                    float *pp = part + 3 * (tb * maxN + qq);
+                    pp[0] = gx;
+                    pp[1] = gy;
+                    pp[2] = gt;
+                }
+            }
+            __syncthreads();
+            // 3. reverse recursion over the block's steps, one thread per
+            // controlled object
+            if (q < NC) {
+                const int i = i_own;
+                const long g = g_own;
+                for (int t = tb_hi; t > tb_lo; --t) {
+                    const int tb = t - tb_lo - 1, at = tb * maxN + i;
+                    const float *pp = part + 3 * (tb * maxN + q);
+                    const float *r = rec + kBwdRec * (tb * maxN + q);
+                    bx += w * pp[0];
+                    by += w * pp[1];
+                    byaw += w * pp[2];
+                    const float4 pa = st4[at];
+                    if (r[2] != 0.f) {
+                        bx += w * 2.f * (pa.x - r[0]);
+                        by += w * 2.f * (pa.y - r[1]);
+                    }
+                    // previous state (t - 1) and the action of step t
+                    const float yaw0 = r[3], vx0 = r[4], vy0 = r[5];
+                    const float a = r[6], k = r[7];
+                    const float v = sqrtf(__builtin_fmaf(vy0, vy0, vx0 * vx0));
+                    const float dist = __builtin_fmaf(v, dt, a * hdt2);
+                    const float nv = __builtin_fmaf(a, dt, v);
+                    const float ns = pa.w, nc = pa.z;   // sin, cos of the yaw at t
+                    float s0, c0;
+                    sincosf(yaw0, &s0, &c0);
+                    const float bnv = __builtin_fmaf(bvx, nc, bvy * ns);
+                    const float tyaw = byaw + nv * __builtin_fmaf(bvy, nc, -(bvx * ns));
+                    const float ga_ =
+                        __builtin_fmaf(hdt2, __builtin_fmaf(bx, c0, __builtin_fmaf(by, s0, k * tyaw)), dt * bnv);
+                    const float gk_ = dist * tyaw;
+                    const float pyaw = tyaw + a * hdt2 * __builtin_fmaf(by, c0, -(bx * s0));
+                    const float bv = __builtin_fmaf(k * dt, tyaw, bnv);
+                    const float inv = v > 0.f ? bv / v : 0.f;
+                    A.grad_a[(long)(t - 1) * n + g] = ga_;
+                    A.grad_k[(long)(t - 1) * n + g] = gk_;
+                    byaw = pyaw;
+                    bvx = __builtin_fmaf(dt, bx, inv * vx0);
+                    bvy = __builtin_fmaf(dt, by, inv * vy0);
+                }
+            }
+            __syncthreads();   // the block's LDS is reused by the next block
         }
     }
 }
 
-static size_t backward_lds(int maxN)
+// Steps per LDS block for this object bound and checkpoint interval.
+int backward_block_steps(int maxN, int K)
 {
-    const size_t ps = maxN > kBwdThreads ? (size_t)maxN : (size_t)kBwdThreads;
-    return align_up((size_t)maxN * (9 + 5) * 4 + 3 * ps * 4 + (size_t)maxN * 4 + 2 * (size_t)maxN, 16);
+    const size_t per_step = (size_t)maxN * kBwdStepBytes;
+    int sb = (int)(kBwdStageBudget / (per_step > 0 ? per_step : 1));
+    return sb < 1 ? 1 : (sb > K ? K : sb);
+}
+
+static size_t backward_lds(int maxN, int SB)
+{
+    return align_up((size_t)SB * maxN * kBwdStepBytes + (size_t)maxN * 4, 16);
 }
 
 void launch_backward(const BackwardArgs &a, hipStream_t st)
 {
-    const size_t lds = backward_lds(a.maxN);
+    const size_t lds = backward_lds(a.maxN, a.SB);
     if (lds > 65536)
         // a failure here makes the launch below fail, which the caller reports
         (void)hipFuncSetAttribute((const void *)k_rollout_backward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -107,6 +107,7 @@ struct ObserveArgs {
 
 struct BackwardArgs {
     int S, n, T, K, maxN;
+    int SB;          // steps per LDS block (backward_block_steps)
     float dt;
     const int32_t *obj_off;
     wm_state init;
@@ -176,6 +177,7 @@ void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controll
                       hipStream_t st);
 void launch_loss_reduce(int S, const int32_t *uoff, const float *lossp, float *loss, hipStream_t st);
 void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream_t st);
+int backward_block_steps(int maxN, int K);
 void launch_backward(const BackwardArgs &a, hipStream_t st);
 
 } // namespace wm
