@@ -56,6 +56,27 @@ def rollout_ops(scene, T):
     return per_step * T, float((4.0 * N * E).sum() * T)
 
 
+# Algorithmic FP32 ops of the adjoint (FMA = 2): per ordered pair (controlled
+# object, valid partner) and step, the separating-axis margin (49: offsets 2,
+# relative rotation 6, absolute values 2, four projections 12, four gaps 24,
+# minimum 3), the gradient through the arg-min axis (9), the sigmoid and its
+# derivative (7) and the accumulation (6): 71; per controlled object and step,
+# the recomputed bicycle step (20) and its adjoint with the log term (50): 70.
+ADJ_OPS_PER_PAIR = 71
+ADJ_OPS_PER_OBJECT = 70
+
+
+def adjoint_ops(scene, controlled):
+    """Algorithmic ops of one adjoint launch over the scene's T steps; every
+    object is valid in the synthetic scenes."""
+    ctrl = np.asarray(controlled).astype(bool)
+    off = np.asarray(scene.obj_off)
+    nc = np.add.reduceat(ctrl.astype(np.int64), off[:-1]) if len(off) > 1 else np.zeros(0)
+    N = np.diff(off).astype(np.int64)
+    pairs = float((nc * np.maximum(N - 1, 0)).sum())
+    return scene.steps * (ADJ_OPS_PER_PAIR * pairs + ADJ_OPS_PER_OBJECT * float(nc.sum())), scene.steps * pairs
+
+
 # The sources k_rollout is compiled from: its counters stay valid while these
 # and the tuning are unchanged.
 ROLLOUT_SOURCES = ("paper_2310_08710_amd/csrc/wm_kernels.hip", "paper_2310_08710_amd/csrc/wm_device.h",
@@ -406,10 +427,16 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
     fbms = 1e3 * (time.perf_counter() - t0) / reps
     bms, bl = wm.profile_collect(wm.PROF_BACKWARD)
     wm.profile_enable(False)
+    bkm = bms / max(bl, 1)
+    aops, apairs = adjoint_ops(scene, ds.act_seq.controlled.cpu().numpy())
     out["fwd_bwd"] = {"value": S * T / (fbms * 1e-3), "unit": "rollout scenario-steps/s",
                       "agent_steps_per_s": n * T / (fbms * 1e-3), "ms_per_rollout": fbms,
-                      "backward_kernel_ms": bms / max(bl, 1), "controlled": "all objects",
-                      "checkpoint_every": 10}
+                      "backward_kernel_ms": bkm, "controlled": "all objects",
+                      "checkpoint_every": 10,
+                      "backward_roofline": {"bound": "alu", "achieved": aops / (bkm * 1e-3) / 1e12,
+                                            "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                                            "frac": aops / (bkm * 1e-3) / PEAK_FP32, "ops_per_launch": aops,
+                                            "pair_terms_per_launch": apairs}}
     log("fwd+bwd: %.3f ms/rollout (adjoint kernel %.3f ms)" % (fbms, bms / max(bl, 1)))
 
     observation(out, scene, ds, dev, traj2, reps)
@@ -456,8 +483,11 @@ def fwd_bwd_config3(out, dev, reps=3):
         bms, bl = wm.profile_collect(wm.PROF_BACKWARD)
         fms, fl = wm.profile_collect(wm.PROF_ROLLOUT)
         wm.profile_enable(False)
+        bkm = bms / max(bl, 1)
+        aops, _ = adjoint_ops(sc, sc.controlled)
         res[key] = {"value": S * T / (ms * 1e-3), "agent_steps_per_s": sc.total_objects * T / (ms * 1e-3),
-                    "ms_per_rollout": ms, "forward_kernel_ms": fms / max(fl, 1), "backward_kernel_ms": bms / max(bl, 1)}
+                    "ms_per_rollout": ms, "forward_kernel_ms": fms / max(fl, 1), "backward_kernel_ms": bkm,
+                    "backward_tflops": aops / (bkm * 1e-3) / 1e12, "backward_frac": aops / (bkm * 1e-3) / PEAK_FP32}
         log("fwd+bwd (512 x 128, 8 controlled, %s): %.3f ms/rollout (forward kernel %.3f ms, adjoint %.3f ms)" % (
             key, ms, fms / max(fl, 1), bms / max(bl, 1)))
     res["value"] = res["full_metrics"]["value"]
