@@ -354,19 +354,25 @@ __device__ __forceinline__ void scan_edges(const float *__restrict__ stream, int
     }
 }
 
-// Exact rescan of chunk `c` for one corner (per lane): lowest index of the
-// minimum of D over the chunk's real points (index < E), folded into
-// (best, bidx) with strict <, so chunks rescanned in ascending order keep the
-// lowest index.  The chunk's x and y columns arrive as 16-byte vector loads
-// (chunks are 16-byte aligned in the workspace).
-__device__ __forceinline__ void rescan_chunk(const float *__restrict__ stream, int c, int E, float cx, float cy,
-                                             float &best, int &bidx)
+// Exact rescan of part rl (of kRescanLanes) of chunk `c` for one corner:
+// the lowest index of the minimum of D over the part's real points (index <
+// E), points c * kChunk + rl * kRescanPart + k in ascending k, folded into
+// (best, bidx) with strict <; a (D, index) reduction over the parts then
+// gives the chunk's lowest-index minimum, and chunks rescanned in ascending
+// order keep the lowest index.  The x and y columns arrive as 16-byte vector
+// loads (chunks are 16-byte aligned in the workspace).
+constexpr int kRescanLanes = 8;
+constexpr int kRescanPart = kChunk / kRescanLanes;   // 16 points
+static_assert(kRescanPart % 4 == 0, "a part is whole float4 groups");
+
+__device__ __forceinline__ void rescan_part(const float *__restrict__ stream, int c, int rl, int E, float cx,
+                                            float cy, float &best, int &bidx)
 {
-    const float4 *px = (const float4 *)(stream + kChunkFloats * c);
-    const float4 *py = (const float4 *)(stream + kChunkFloats * c + kChunk);
-    const int n = E - kChunk * c;
+    const float4 *px = (const float4 *)(stream + kChunkFloats * c) + rl * (kRescanPart / 4);
+    const float4 *py = (const float4 *)(stream + kChunkFloats * c + kChunk) + rl * (kRescanPart / 4);
+    const int n = E - kChunk * c - rl * kRescanPart;   // points of this part inside the stream
 #pragma unroll
-    for (int b = 0; b < kChunk / 4; ++b) {
+    for (int b = 0; b < kRescanPart / 4; ++b) {
         const float4 X = px[b], Y = py[b];
         const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w};
 #pragma unroll
@@ -375,7 +381,7 @@ __device__ __forceinline__ void rescan_chunk(const float *__restrict__ stream, i
             const float d = edge_d2(xs[k], ys[k], cx, cy);
             if (j < n && d < best) {
                 best = d;
-                bidx = kChunk * c + j;
+                bidx = kChunk * c + rl * kRescanPart + j;
             }
         }
     }

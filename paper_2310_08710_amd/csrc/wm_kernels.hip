@@ -296,14 +296,14 @@ __device__ __forceinline__ void scan_r(const float *stream, int c0, int c1, floa
 
 // Off-road scan of the 4*Ns corners of slice objects i0.. against one
 // scenario's compacted edges (stream/dir/idx already offset to the scenario,
-// E edges, qqmax), then the exact rescan of the candidate chunks that yields
-// the lowest-index nearest point and the signed side of every corner.
-// Waves: w = tid / 64, corner wave cw = w % CW (256 corner slots each), edge
-// split g = w / CW (contiguous chunk ranges in index order).  Leaves sk[slot]
-// and nidx[slot] (scenario-local point index or -1) for slot < 4*Ns.
-// Contains two block barriers, plus two per corner that needs the exact scan
-// of every point (their count is read by every thread after a barrier, so
-// the barriers are uniform).
+// E edges, qqmax), then the exact rescan of the candidate chunks (8 lanes per
+// corner) that yields the lowest-index nearest point and the signed side of
+// every corner.  Waves: w = tid / 64, corner wave cw = w % CW (256 corner
+// slots each), edge split g = w / CW (contiguous chunk ranges in index
+// order).  Leaves sk[slot] and nidx[slot] (scenario-local point index or -1)
+// for slot < 4*Ns.  Contains three block barriers, plus two per corner that
+// needs the exact scan of every point (their count is read by every thread
+// after a barrier, so the barriers are uniform).
 __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
                              const float2 *__restrict__ edir, const int32_t *__restrict__ eidx, int E, float qqmax,
                              int G, int CW, ScanLds C, float *sk, int *nidx)
@@ -366,8 +366,7 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
             }
         }
         const int o = i0 + (slot >> 2);
-        float s_val = kNoValue;
-        int near = -1;
+        int lo = -1, hi = -1;   // candidate chunks; lo: -1 none, -2 the exact scan of every point
         if (bc >= 0 && L.valid[o]) {
             float x, y;
             box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
@@ -389,27 +388,60 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
                     }
                 }
             }
-            float best = __builtin_inff();
-            int bj = -1;
             if (full) {
-                // rare: left to the whole work-group after the next barrier
+                // rare: left to the whole work-group after the rescans
                 C.full[atomicAdd(C.nfull, 1)] = slot;
+                lo = -2;
             } else {
-                const int lo = other >= 0 ? min(bc, other) : bc;
-                rescan_chunk(stream, lo, E, x, y, best, bj);
-                if (other >= 0)
-                    rescan_chunk(stream, max(bc, other), E, x, y, best, bj);
+                lo = other >= 0 ? min(bc, other) : bc;
+                hi = other >= 0 ? max(bc, other) : -1;
             }
-            if (bj >= 0) {
+        }
+        // the candidate chunks wait in the slot's outputs for the rescan
+        nidx[slot] = lo;
+        sk[slot] = __int_as_float(hi);
+    }
+    __syncthreads();
+    // the exact rescan of the one or two candidate chunks of every corner:
+    // kRescanLanes lanes per corner, each 128 / kRescanLanes points of a
+    // chunk in ascending order (strict <), then a (D, index) reduction over
+    // the corner's lanes that keeps the lowest index of the minimum
+    for (int u0 = 0; u0 < nslots * kRescanLanes; u0 += blockDim.x) {   // block-uniform trip count
+        const int u = u0 + tid, slot = u / kRescanLanes, rl = u % kRescanLanes;
+        const bool act = slot < nslots;
+        const int lo = act ? nidx[slot] : -1, hi = act ? __float_as_int(sk[slot]) : -1;
+        float best = __builtin_inff(), x = 0.f, y = 0.f;
+        int bj = 0x7fffffff;
+        if (lo >= 0) {
+            const int o = i0 + (slot >> 2);
+            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+            rescan_part(stream, lo, rl, E, x, y, best, bj);
+            if (hi >= 0)
+                rescan_part(stream, hi, rl, E, x, y, best, bj);
+        }
+        for (int off = kRescanLanes / 2; off > 0; off >>= 1) {
+            const float ob = __shfl_xor(best, off);
+            const int oj = __shfl_xor(bj, off);
+            if (ob < best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if (act && rl == 0) {
+            // corners for the exact scan of every point keep these defaults
+            // until it finds a point
+            float s_val = kNoValue;
+            int near = -1;
+            if (lo >= 0 && bj != 0x7fffffff) {
                 const float *ch = stream + kChunkFloats * (bj / kChunk) + (bj % kChunk);
                 const float qx = ch[0], qy = ch[kChunk];
                 const float2 d = edir[bj];
                 s_val = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
                 near = eidx[bj];
             }
+            sk[slot] = s_val;
+            nidx[slot] = near;
         }
-        sk[slot] = s_val;
-        nidx[slot] = near;
     }
     __syncthreads();
     // corners with three or more candidate chunks (rare): an exact scan of
