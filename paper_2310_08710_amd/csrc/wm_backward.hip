@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                     const Box bi{pi.x, pi.y, pi.z, pi.w, hi.x, hi.y};
                     const float4 *row4 = st4 + tb * maxN;
                     const float2 *row2 = st2 + tb * maxN;
-                    // the partners j = gl, gl + G, ... in ascending order, two
+                    // the partners j = gl, gl + G, ... in ascending order, four
                     // per iteration; a term of j == i or of an invalid j is 0
                     auto term = [&](int j, float &tx, float &ty, float &tt) {
                         const float4 pj = row4[j];
@@ -244,18 +244,19 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                         tt = ok ? dm * ut : 0.f;
                     };
                     int j = gl;
-                    for (; j + G < N; j += 2 * G) {
-                        float ax, ay, at, bx2, by2, bt;
-                        term(j, ax, ay, at);
-                        term(j + G, bx2, by2, bt);
-                        gx += ax;
-                        gy += ay;
-                        gt += at;
-                        gx += bx2;
-                        gy += by2;
-                        gt += bt;
+                    for (; j + 3 * G < N; j += 4 * G) {
+                        float tx[4], ty[4], tt[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            term(j + e * G, tx[e], ty[e], tt[e]);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            gx += tx[e];
+                            gy += ty[e];
+                            gt += tt[e];
+                        }
                     }
-                    if (j < N) {
+                    for (; j < N; j += G) {
                         float ax, ay, at;
                         term(j, ax, ay, at);
                         gx += ax;
