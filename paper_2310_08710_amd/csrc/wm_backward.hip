@@ -235,7 +235,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                         // the pair's margin with the lower index first, as in the forward
                         const float m = i < j ? sat_margin_grad_one(bi, bj, false, ux, uy, ut)
                                               : sat_margin_grad_one(bj, bi, true, ux, uy, ut);
-                        const float sg = 1.0f / (1.0f + expf(-m * (1.0f / kSoftScale)));
+                        // the sigmoid's derivative only scales a gradient term:
+                        // the hardware exponential and reciprocal (about 1 ulp)
+                        const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-m * (1.0f / kSoftScale)));
                         const float dm = sg * (1.0f - sg) * (1.0f / kSoftScale);
                         // selects, not products: an invalid object's values may be anything
                         const bool ok = j != i && hj.x >= 0.f;
