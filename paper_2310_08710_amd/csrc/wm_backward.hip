@@ -33,55 +33,6 @@ constexpr size_t kBwdStageBudget = 96 * 1024;   // LDS for the SB-step blocks
 constexpr int kBwdRec = 8;                       // recursion inputs per (step, controlled object)
 constexpr size_t kBwdStepBytes = 16 + 8 + 3 * 4 + kBwdRec * 4;   // LDS per step and object
 
-// Margin of the separating-axis test (the same value as sat_margin) and its
-// gradient with respect to (x, y, yaw) of box a (of_b false) or box b (of_b
-// true), through the arg-min axis (lowest axis index on ties), sgn(0) = +1,
-// as sat_margin_grad.
-__device__ __forceinline__ float sat_margin_grad_one(const Box &a, const Box &b, bool of_b, float &gx, float &gy,
-                                                     float &gt)
-{
-    const float dx = b.x - a.x, dy = b.y - a.y;
-    const float cd = __builtin_fmaf(a.c, b.c, a.s * b.s);    // cos(delta), delta = yaw_b - yaw_a
-    const float sd = __builtin_fmaf(a.c, b.s, -(a.s * b.c)); // sin(delta)
-    const float C = fabsf(cd), S = fabsf(sd);
-    const float dC = -(cd >= 0.f ? 1.f : -1.f) * sd;
-    const float dS = (sd >= 0.f ? 1.f : -1.f) * cd;
-    const float pua = __builtin_fmaf(dx, a.c, dy * a.s), pwa = __builtin_fmaf(dy, a.c, -(dx * a.s));
-    const float pub = __builtin_fmaf(dx, b.c, dy * b.s), pwb = __builtin_fmaf(dy, b.c, -(dx * b.s));
-    const float g0 = a.hl + __builtin_fmaf(b.hl, C, b.hw * S) - fabsf(pua);
-    const float g1 = a.hw + __builtin_fmaf(b.hl, S, b.hw * C) - fabsf(pwa);
-    const float g2 = b.hl + __builtin_fmaf(a.hl, C, a.hw * S) - fabsf(pub);
-    const float g3 = b.hw + __builtin_fmaf(a.hl, S, a.hw * C) - fabsf(pwb);
-    // arg-min with selects (lowest index on ties)
-    const bool k1 = g1 < g0;
-    float m = k1 ? g1 : g0;
-    const bool k2 = g2 < m;
-    m = k2 ? g2 : m;
-    const bool k3 = g3 < m;
-    m = k3 ? g3 : m;
-    const int k = k3 ? 3 : (k2 ? 2 : (k1 ? 1 : 0));
-    const bool on_a = k < 2, odd = (k & 1) != 0;
-    // axis (ax, ay), projection p of the offset on it, d(radius)/d(delta) rd,
-    // and d(p)/d(own yaw) of the box whose axis it is
-    const float bc = on_a ? a.c : b.c, bs = on_a ? a.s : b.s;
-    const float ax = odd ? -bs : bc, ay = odd ? bc : bs;
-    const float p = on_a ? (odd ? pwa : pua) : (odd ? pwb : pub);
-    const float hl = on_a ? b.hl : a.hl, hw = on_a ? b.hw : a.hw;
-    const float rd = odd ? __builtin_fmaf(hl, dS, hw * dC) : __builtin_fmaf(hl, dC, hw * dS);
-    const float dp = on_a ? (odd ? -pua : pwa) : (odd ? -pub : pwb);
-    const float sp = p >= 0.f ? 1.f : -1.f;
-    if (!of_b) {
-        gx = sp * ax;
-        gy = sp * ay;
-        gt = -rd - (on_a ? sp * dp : 0.f);
-    } else {
-        gx = -sp * ax;
-        gy = -sp * ay;
-        gt = rd - (on_a ? 0.f : sp * dp);
-    }
-    return m;
-}
-
 __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];

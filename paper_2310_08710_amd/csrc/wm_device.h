@@ -177,9 +177,11 @@ __device__ __forceinline__ float idm_accel(const wm_idm &p, float v, bool lead, 
     return fminf(fmaxf(a, -p.max_brake), p.max_accel);
 }
 
-// Gradient of sat_margin with respect to (x, y, yaw) of a and of b, through
-// the arg-min axis (lowest axis index on ties), sgn(0) = +1.
-__device__ __forceinline__ void sat_margin_grad(const Box &a, const Box &b, float ga[3], float gb[3])
+// Margin of the separating-axis test (the same value as sat_margin) and its
+// gradient with respect to (x, y, yaw) of box a (of_b false) or box b (of_b
+// true), through the arg-min axis (lowest axis index on ties), sgn(0) = +1.
+__device__ __forceinline__ float sat_margin_grad_one(const Box &a, const Box &b, bool of_b, float &gx, float &gy,
+                                                     float &gt)
 {
     const float dx = b.x - a.x, dy = b.y - a.y;
     const float cd = __builtin_fmaf(a.c, b.c, a.s * b.s);    // cos(delta), delta = yaw_b - yaw_a
@@ -189,33 +191,38 @@ __device__ __forceinline__ void sat_margin_grad(const Box &a, const Box &b, floa
     const float dS = (sd >= 0.f ? 1.f : -1.f) * cd;
     const float pua = __builtin_fmaf(dx, a.c, dy * a.s), pwa = __builtin_fmaf(dy, a.c, -(dx * a.s));
     const float pub = __builtin_fmaf(dx, b.c, dy * b.s), pwb = __builtin_fmaf(dy, b.c, -(dx * b.s));
-    const float g[4] = {
-        a.hl + __builtin_fmaf(b.hl, C, b.hw * S) - fabsf(pua),
-        a.hw + __builtin_fmaf(b.hl, S, b.hw * C) - fabsf(pwa),
-        b.hl + __builtin_fmaf(a.hl, C, a.hw * S) - fabsf(pub),
-        b.hw + __builtin_fmaf(a.hl, S, a.hw * C) - fabsf(pwb),
-    };
-    int k = 0;
-    if (g[1] < g[k]) k = 1;
-    if (g[2] < g[k]) k = 2;
-    if (g[3] < g[k]) k = 3;
-    float ax, ay, p, rd, dpa = 0.f, dpb = 0.f;
-    if (k == 0) {
-        ax = a.c; ay = a.s; p = pua; rd = __builtin_fmaf(b.hl, dC, b.hw * dS); dpa = pwa;
-    } else if (k == 1) {
-        ax = -a.s; ay = a.c; p = pwa; rd = __builtin_fmaf(b.hl, dS, b.hw * dC); dpa = -pua;
-    } else if (k == 2) {
-        ax = b.c; ay = b.s; p = pub; rd = __builtin_fmaf(a.hl, dC, a.hw * dS); dpb = pwb;
-    } else {
-        ax = -b.s; ay = b.c; p = pwb; rd = __builtin_fmaf(a.hl, dS, a.hw * dC); dpb = -pub;
-    }
+    const float g0 = a.hl + __builtin_fmaf(b.hl, C, b.hw * S) - fabsf(pua);
+    const float g1 = a.hw + __builtin_fmaf(b.hl, S, b.hw * C) - fabsf(pwa);
+    const float g2 = b.hl + __builtin_fmaf(a.hl, C, a.hw * S) - fabsf(pub);
+    const float g3 = b.hw + __builtin_fmaf(a.hl, S, a.hw * C) - fabsf(pwb);
+    // arg-min with selects (lowest index on ties)
+    const bool k1 = g1 < g0;
+    float m = k1 ? g1 : g0;
+    const bool k2 = g2 < m;
+    m = k2 ? g2 : m;
+    const bool k3 = g3 < m;
+    m = k3 ? g3 : m;
+    const int k = k3 ? 3 : (k2 ? 2 : (k1 ? 1 : 0));
+    const bool on_a = k < 2, odd = (k & 1) != 0;
+    // axis (ax, ay), projection p of the offset on it, d(radius)/d(delta) rd,
+    // and d(p)/d(own yaw) of the box whose axis it is
+    const float bc = on_a ? a.c : b.c, bs = on_a ? a.s : b.s;
+    const float ax = odd ? -bs : bc, ay = odd ? bc : bs;
+    const float p = on_a ? (odd ? pwa : pua) : (odd ? pwb : pub);
+    const float hl = on_a ? b.hl : a.hl, hw = on_a ? b.hw : a.hw;
+    const float rd = odd ? __builtin_fmaf(hl, dS, hw * dC) : __builtin_fmaf(hl, dC, hw * dS);
+    const float dp = on_a ? (odd ? -pua : pwa) : (odd ? -pub : pwb);
     const float sp = p >= 0.f ? 1.f : -1.f;
-    ga[0] = sp * ax;
-    ga[1] = sp * ay;
-    gb[0] = -sp * ax;
-    gb[1] = -sp * ay;
-    ga[2] = -rd - sp * dpa;
-    gb[2] = rd - sp * dpb;
+    if (!of_b) {
+        gx = sp * ax;
+        gy = sp * ay;
+        gt = -rd - (on_a ? sp * dp : 0.f);
+    } else {
+        gx = -sp * ax;
+        gy = -sp * ay;
+        gt = rd - (on_a ? 0.f : sp * dp);
+    }
+    return m;
 }
 
 // Corner k of a box: 0 front-left, 1 front-right, 2 rear-right, 3 rear-left.
