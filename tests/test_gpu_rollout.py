@@ -178,6 +178,33 @@ def test_adjoint_matches_oracle_gradient():
     assert np.abs(oga).max() > 0.1                  # the gradient is not trivially zero
 
 
+def test_adjoint_scenario_without_controlled_objects():
+    """A scenario with no controlled object contributes nothing: its
+    gradients are zero and the other scenarios' match the oracle."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _grad_scene(T=9)
+    sc.controlled[sc.obj_off[1]:sc.obj_off[2]] = 0
+    ds = wm.upload(sc, dev)
+    T = sc.steps
+    a = ds.act_seq.accel.clone().requires_grad_(True)
+    k = ds.act_seq.curvature.clone().requires_grad_(True)
+    loss = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, None, T, sc.dt, 4, None)
+    loss.sum().backward()
+    torch.cuda.synchronize()
+    lw = sc.log_window()
+    oga, ogk, _ = oracle.rollout_grad(sc.obj_off, f64({q: v[0] for q, v in lw.items()}), sc.accel, sc.curvature,
+                                      sc.controlled, f64(lw), T, sc.dt)
+    ga, gk = a.grad.cpu().numpy(), k.grad.cpu().numpy()
+    c1 = slice(sc.obj_off[1], sc.obj_off[2])
+    assert (ga[:, c1] == 0).all() and (gk[:, c1] == 0).all()
+    for s in (0, 2, 3):
+        cols = slice(sc.obj_off[s], sc.obj_off[s + 1])
+        for g, o in ((ga, oga), (gk, ogk)):
+            assert np.linalg.norm(g[:, cols] - o[:, cols]) <= 1e-3 * np.linalg.norm(o[:, cols]), s
+
+
 def test_adjoint_checkpoint_interval_invariance():
     import torch
     from paper_2310_08710_amd import wm
@@ -337,7 +364,7 @@ def test_observe_when_the_sampled_bound_misleads():
 
 
 def test_observe_small_and_odd_point_counts():
-    """Scenarios of 1, 2, 3, 5, 4,097 and 6,143 road points (the last round
+    """Scenarios of 0, 1, 2, 3, 5, 4,097 and 6,143 road points (the last round
     of the 1024-thread work-group is partial; loads past a scenario's end are
     clamped), k = 4 and k = 1000, so that k exceeds the valid points of some
     scenarios; some points invalid.  Again with the road-graph arrays 4 bytes
@@ -345,7 +372,7 @@ def test_observe_small_and_odd_point_counts():
     import torch
     from paper_2310_08710_amd import wm
     dev = device()
-    counts = [1, 2, 3, 5, 4097, 6143]
+    counts = [0, 1, 2, 3, 5, 4097, 6143]
     sc = synth.make_scene(4, scenarios=len(counts), objects=(3, 9), rg_points=(24, 24), steps=2)
     rng = np.random.default_rng(5)
     P = np.asarray(counts)
@@ -354,7 +381,7 @@ def test_observe_small_and_odd_point_counts():
     sc.rg = {"x": rng.uniform(-60, 60, tot).astype(np.float32), "y": rng.uniform(-60, 60, tot).astype(np.float32),
              "dir_x": np.ones(tot, np.float32), "dir_y": np.zeros(tot, np.float32),
              "type": np.ones(tot, np.int8), "valid": (rng.random(tot) > 0.1).astype(np.uint8)}
-    sc.rg["valid"][0] = 1
+    sc.rg["valid"][int(P[0])] = 1
     st = sc.state_at(synth.T0)
     ds = wm.upload(sc, dev)
     S, E = sc.num_scenarios, sc.ego.shape[1]
