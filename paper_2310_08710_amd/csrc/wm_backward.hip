@@ -16,9 +16,12 @@
 //      lane + G, ...) and sums them with a fixed shuffle tree;
 //   3. one thread per controlled object runs the reverse recursion over the
 //      SB steps: the log-divergence term 2 (p - p_log), then back through the
-//      bicycle step, with the object's adjoint held in registers and its
-//      inputs (log position, previous state, action), which do not depend on
-//      the adjoint, staged in LDS with the states.
+//      bicycle step, with the object's adjoint held in registers.  Its
+//      inputs do not depend on the adjoint and are staged in LDS with the
+//      states: the log position, and the factors of the step's derivatives
+//      that the previous state and the action give (sine and cosine of the
+//      previous yaw, speeds, distance, velocity direction), computed in
+//      parallel so that the recursion's chain holds no transcendental.
 // G depends only on the scenario's object count and SB only changes the
 // blocking, so the gradients are identical for every checkpoint interval.
 // Only controlled, valid objects carry adjoints: replayed objects do not
@@ -29,22 +32,36 @@
 namespace wm {
 
 constexpr int kBwdThreads = 1024;
-constexpr size_t kBwdStageBudget = 96 * 1024;   // LDS for the SB-step blocks
-constexpr int kBwdRec = 8;                       // recursion inputs per (step, controlled object)
+constexpr size_t kBwdStageBudget = 112 * 1024;   // LDS for the SB-step blocks
+constexpr int kBwdRec = 12;                       // recursion inputs per (step, controlled object)
+static_assert(kBwdRec % 4 == 0, "the recursion inputs are read as float4");
 constexpr size_t kBwdStepBytes = 16 + 8 + 3 * 4 + kBwdRec * 4;   // LDS per step and object
+static_assert(WM_MAX_OBJECTS <= kBwdThreads, "one thread per controlled object");
+
+__device__ __forceinline__ void store_state(float *row, long n, long g, float x, float y, float yaw, float vx, float vy)
+{
+    row[g] = x;
+    row[n + g] = y;
+    row[2 * n + g] = yaw;
+    row[3 * n + g] = vx;
+    row[4 * n + g] = vy;
+}
 
 __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int maxN = A.maxN, SB = A.SB;
-    // LDS: [SB][maxN] (x, y, cos, sin) and (half length or -1 when invalid,
-    // half width); the pair-term sums [SB][maxN][3] and the recursion's
-    // inputs [SB][maxN][8] per controlled slot; the controlled objects' indices
+    // LDS: [SB][maxN] (x, y, cos, sin), the recursion's inputs [SB][maxN][12]
+    // per controlled slot (16-byte aligned), [SB][maxN] (half length or -1
+    // when invalid, half width), the pair-term sums [SB][maxN][3]; the
+    // controlled objects' indices; per object 2 (controlled and valid), 1
+    // (controlled, invalid) or 0 (from the log)
     float4 *st4 = (float4 *)smem;
-    float2 *st2 = (float2 *)(st4 + SB * maxN);
+    float *rec = (float *)(st4 + SB * maxN);
+    float2 *st2 = (float2 *)(rec + kBwdRec * SB * maxN);
     float *part = (float *)(st2 + SB * maxN);
-    float *rec = part + 3 * SB * maxN;
-    int *cidx = (int *)(rec + kBwdRec * SB * maxN);
+    int *cidx = (int *)(part + 3 * SB * maxN);
+    uint8_t *kind = (uint8_t *)(cidx + maxN);
     __shared__ int s_nc;
 
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -62,7 +79,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
         s_nc = nc;
     }
     for (int i = tid; i < N; i += nthr) {
-        const bool live = A.act.controlled[o0 + i] && A.init.valid[o0 + i];
+        const bool ctl = A.act.controlled[o0 + i] != 0, live = ctl && A.init.valid[o0 + i];
+        kind[i] = ctl ? (live ? 2 : 1) : 0;
         if (!live)
             for (int t = 0; t < A.T; ++t) {
                 A.grad_a[(long)t * n + o0 + i] = 0.f;
@@ -87,24 +105,37 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
     for (int c = nseg - 1; c >= 0; --c) {
         const int t0 = c * A.K, t1 = min(A.T, t0 + A.K);
         __syncthreads();   // the previous block's readers of seg are done
-        // recompute the controlled objects' states t0..t1 into the workspace
-        for (int qq = tid; qq < NC; qq += nthr) {
-            const long g = o0 + cidx[qq];
-            float x = A.ckpt.x[(long)c * n + g], y = A.ckpt.y[(long)c * n + g], yaw = A.ckpt.yaw[(long)c * n + g];
-            float vx = A.ckpt.vx[(long)c * n + g], vy = A.ckpt.vy[(long)c * n + g];
-            for (int t = t0; t <= t1; ++t) {
-                if (t > t0)
-                    bicycle_forward(x, y, yaw, vx, vy, A.act.accel[(long)(t - 1) * n + g],
-                                    A.act.curvature[(long)(t - 1) * n + g], dt);
-                float *row = seg + (long)(t - t0) * 5 * n;
-                row[g] = x;
-                row[n + g] = y;
-                row[2 * n + g] = yaw;
-                row[3 * n + g] = vx;
-                row[4 * n + g] = vy;
-            }
+        // recompute the controlled objects' states t0..t1 into the workspace,
+        // thread q for controlled object q.  The actions go to the (free)
+        // block LDS first, RC steps at a time, so that their loads are in
+        // flight together rather than one step after another.
+        float sx = 0.f, sy = 0.f, syaw = 0.f, svx = 0.f, svy = 0.f;
+        if (q < NC) {
+            sx = A.ckpt.x[(long)c * n + g_own];
+            sy = A.ckpt.y[(long)c * n + g_own];
+            syaw = A.ckpt.yaw[(long)c * n + g_own];
+            svx = A.ckpt.vx[(long)c * n + g_own];
+            svy = A.ckpt.vy[(long)c * n + g_own];
+            store_state(seg, n, g_own, sx, sy, syaw, svx, svy);
         }
-        __syncthreads();
+        float2 *acts = (float2 *)smem;
+        const int RC = (int)((size_t)SB * maxN * kBwdStepBytes / sizeof(float2) / max(NC, 1));
+        for (int tc = t0; tc < t1; tc += RC) {   // steps tc + 1 .. tc + nr
+            const int nr = min(RC, t1 - tc);
+            for (int it = tid; it < nr * NC; it += nthr) {
+                const int r = it / NC, qq = it - r * NC;
+                const long at = (long)(tc + r) * n + o0 + cidx[qq];
+                acts[it] = make_float2(A.act.accel[at], A.act.curvature[at]);
+            }
+            __syncthreads();
+            if (q < NC)
+                for (int r = 0; r < nr; ++r) {
+                    const float2 ak = acts[r * NC + q];
+                    bicycle_forward(sx, sy, syaw, svx, svy, ak.x, ak.y, dt);
+                    store_state(seg + (long)(tc + r + 1 - t0) * 5 * n, n, g_own, sx, sy, syaw, svx, svy);
+                }
+            __syncthreads();   // the actions' readers are done, the states are written
+        }
         // blocks of SB steps, last block first: steps tb_lo + 1 .. tb_hi
         for (int tb_hi = t1; tb_hi > t0; tb_hi -= SB) {
             const int tb_lo = max(t0, tb_hi - SB), nb = tb_hi - tb_lo;
@@ -116,8 +147,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                 const long g = o0 + i, lrow = (long)t * n;
                 float x, y, yaw, len, wid;
                 uint8_t v;
-                if (A.act.controlled[g]) {
-                    v = A.init.valid[g];
+                const int kd = kind[i];
+                if (kd != 0) {
+                    v = kd == 2;
                     len = A.init.length[g];
                     wid = A.init.width[g];
                     if (v) {
@@ -144,21 +176,23 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                 st2[at] = make_float2(v ? 0.5f * len : -1.f, 0.5f * wid);
             }
             // the recursion's inputs, which do not depend on the adjoint: the
-            // log position at t, the state at t - 1 and the action of step t
+            // log position at t and the factors of the bicycle step's
+            // derivatives that come from the state at t - 1 and the action of
+            // step t (computed here, in parallel, off the recursion's chain)
             for (int it = tid; it < nb * NC; it += nthr) {
                 const int tb = it / NC, qq = it - tb * NC;
                 const int t = tb_lo + 1 + tb;
                 const long g = o0 + cidx[qq], lrow = (long)t * n;
                 const float *prow = seg + (long)(t - 1 - t0) * 5 * n;
-                float *r = rec + kBwdRec * (tb * maxN + qq);
-                r[0] = A.log.x[lrow + g];
-                r[1] = A.log.y[lrow + g];
-                r[2] = A.log.valid[lrow + g] ? 1.f : 0.f;
-                r[3] = prow[2 * n + g];
-                r[4] = prow[3 * n + g];
-                r[5] = prow[4 * n + g];
-                r[6] = A.act.accel[(long)(t - 1) * n + g];
-                r[7] = A.act.curvature[(long)(t - 1) * n + g];
+                const float yaw0 = prow[2 * n + g], vx0 = prow[3 * n + g], vy0 = prow[4 * n + g];
+                const float a = A.act.accel[(long)(t - 1) * n + g], k = A.act.curvature[(long)(t - 1) * n + g];
+                const float v = sqrtf(__builtin_fmaf(vy0, vy0, vx0 * vx0));
+                float s0, c0;
+                sincosf(yaw0, &s0, &c0);
+                float4 *r = (float4 *)(rec + kBwdRec * (tb * maxN + qq));
+                r[0] = make_float4(A.log.x[lrow + g], A.log.y[lrow + g], A.log.valid[lrow + g] ? 1.f : 0.f, c0);
+                r[1] = make_float4(s0, __builtin_fmaf(a, dt, v), k, __builtin_fmaf(v, dt, a * hdt2));
+                r[2] = make_float4(a * hdt2, v > 0.f ? vx0 / v : 0.f, v > 0.f ? vy0 / v : 0.f, 0.f);
             }
             __syncthreads();
             // 2. pair terms of every (step, controlled object): item u = (tb,
@@ -238,37 +272,31 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                 for (int t = tb_hi; t > tb_lo; --t) {
                     const int tb = t - tb_lo - 1, at = tb * maxN + i;
                     const float *pp = part + 3 * (tb * maxN + q);
-                    const float *r = rec + kBwdRec * (tb * maxN + q);
+                    const float4 *r = (const float4 *)(rec + kBwdRec * (tb * maxN + q));
                     bx += w * pp[0];
                     by += w * pp[1];
                     byaw += w * pp[2];
-                    const float4 pa = st4[at];
-                    if (r[2] != 0.f) {
-                        bx += w * 2.f * (pa.x - r[0]);
-                        by += w * 2.f * (pa.y - r[1]);
+                    const float4 pa = st4[at], r0 = r[0], r1 = r[1], r2 = r[2];
+                    if (r0.z != 0.f) {
+                        bx += w * 2.f * (pa.x - r0.x);
+                        by += w * 2.f * (pa.y - r0.y);
                     }
-                    // previous state (t - 1) and the action of step t
-                    const float yaw0 = r[3], vx0 = r[4], vy0 = r[5];
-                    const float a = r[6], k = r[7];
-                    const float v = sqrtf(__builtin_fmaf(vy0, vy0, vx0 * vx0));
-                    const float dist = __builtin_fmaf(v, dt, a * hdt2);
-                    const float nv = __builtin_fmaf(a, dt, v);
+                    // factors from the previous state (t - 1) and the action of step t
+                    const float c0 = r0.w, s0 = r1.x, nv = r1.y, k = r1.z, dist = r1.w;
+                    const float ahdt2 = r2.x, ux = r2.y, uy = r2.z;
                     const float ns = pa.w, nc = pa.z;   // sin, cos of the yaw at t
-                    float s0, c0;
-                    sincosf(yaw0, &s0, &c0);
                     const float bnv = __builtin_fmaf(bvx, nc, bvy * ns);
                     const float tyaw = byaw + nv * __builtin_fmaf(bvy, nc, -(bvx * ns));
                     const float ga_ =
                         __builtin_fmaf(hdt2, __builtin_fmaf(bx, c0, __builtin_fmaf(by, s0, k * tyaw)), dt * bnv);
                     const float gk_ = dist * tyaw;
-                    const float pyaw = tyaw + a * hdt2 * __builtin_fmaf(by, c0, -(bx * s0));
+                    const float pyaw = tyaw + ahdt2 * __builtin_fmaf(by, c0, -(bx * s0));
                     const float bv = __builtin_fmaf(k * dt, tyaw, bnv);
-                    const float inv = v > 0.f ? bv / v : 0.f;
                     A.grad_a[(long)(t - 1) * n + g] = ga_;
                     A.grad_k[(long)(t - 1) * n + g] = gk_;
                     byaw = pyaw;
-                    bvx = __builtin_fmaf(dt, bx, inv * vx0);
-                    bvy = __builtin_fmaf(dt, by, inv * vy0);
+                    bvx = __builtin_fmaf(dt, bx, bv * ux);
+                    bvy = __builtin_fmaf(dt, by, bv * uy);
                 }
             }
             __syncthreads();   // the block's LDS is reused by the next block
@@ -286,7 +314,7 @@ int backward_block_steps(int maxN, int K)
 
 static size_t backward_lds(int maxN, int SB)
 {
-    return align_up((size_t)SB * maxN * kBwdStepBytes + (size_t)maxN * 4, 16);
+    return align_up((size_t)SB * maxN * kBwdStepBytes + (size_t)maxN * 5, 16);
 }
 
 void launch_backward(const BackwardArgs &a, hipStream_t st)
