@@ -62,8 +62,42 @@ def rollout_ops(scene, T):
 # minimum 3), the gradient through the arg-min axis (9), the sigmoid and its
 # derivative (7) and the accumulation (6): 71; per controlled object and step,
 # the recomputed bicycle step (20) and its adjoint with the log term (50): 70.
+# The adjoint first tests every (controlled object, partner) pair against a
+# distance bound (offsets 2, squared distance 2, radius sum 3, its square
+# doubled 2, comparison 1: 10) and evaluates the 71-op term only where the
+# term can be non-zero in FP32.
 ADJ_OPS_PER_PAIR = 71
 ADJ_OPS_PER_OBJECT = 70
+ADJ_OPS_PER_TEST = 10
+ADJ_CULL_GAP = 9.0   # metres; the same bound as the kernel's
+
+
+def adjoint_executed_ops(obj_off, controlled, init, log_seq, traj, T):
+    """Ops one adjoint launch executes, and the pair terms it evaluates: every
+    (controlled object, partner) pair is tested at every step, and the terms
+    within the bound sqrt(2) (r_i + r_j + ADJ_CULL_GAP) (r = half length + half
+    width; the pair of an object with itself included) are evaluated.  States:
+    controlled objects from the trajectory, the others from the log.  Scenes
+    of uniform object count."""
+    import torch
+    off = obj_off.cpu().numpy()
+    S, N = len(off) - 1, int(off[1] - off[0])
+    assert (np.diff(off) == N).all(), "uniform object counts only"
+    ctrl = (controlled != 0) & (init.valid != 0)
+    nc = int(ctrl.sum())
+    near = 0
+    for t in range(1, T + 1):
+        x = torch.where(ctrl, traj.x[t - 1], log_seq.x[t]).view(S, N)
+        y = torch.where(ctrl, traj.y[t - 1], log_seq.y[t]).view(S, N)
+        ln = torch.where(ctrl, init.length, log_seq.length[t])
+        wd = torch.where(ctrl, init.width, log_seq.width[t])
+        r = (0.5 * (ln + wd)).view(S, N)
+        d2 = (x[:, :, None] - x[:, None, :]) ** 2 + (y[:, :, None] - y[:, None, :]) ** 2
+        rs = r[:, :, None] + r[:, None, :] + ADJ_CULL_GAP
+        m = (d2 <= 2.0 * rs * rs) & ctrl.view(S, N)[:, :, None]
+        near += int(m.sum())
+    ops = T * (ADJ_OPS_PER_TEST * nc * N + ADJ_OPS_PER_OBJECT * nc) + ADJ_OPS_PER_PAIR * near
+    return float(ops), float(near), float(T * nc * (N - 1))
 
 
 def adjoint_ops(scene, controlled):
@@ -429,14 +463,17 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
     wm.profile_enable(False)
     bkm = bms / max(bl, 1)
     aops, apairs = adjoint_ops(scene, ds.act_seq.controlled.cpu().numpy())
+    # the trajectory of these actions (traj2: the expert rollout, every object controlled)
+    xops, xnear, _ = adjoint_executed_ops(ds.batch.obj_off, ds.act_seq.controlled, ds.init, ds.log_seq, traj2, T)
     out["fwd_bwd"] = {"value": S * T / (fbms * 1e-3), "unit": "rollout scenario-steps/s",
                       "agent_steps_per_s": n * T / (fbms * 1e-3), "ms_per_rollout": fbms,
                       "backward_kernel_ms": bkm, "controlled": "all objects",
                       "checkpoint_every": 10,
-                      "backward_roofline": {"bound": "alu", "achieved": aops / (bkm * 1e-3) / 1e12,
+                      "backward_roofline": {"bound": "alu", "achieved": xops / (bkm * 1e-3) / 1e12,
                                             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                                            "frac": aops / (bkm * 1e-3) / PEAK_FP32, "ops_per_launch": aops,
-                                            "pair_terms_per_launch": apairs}}
+                                            "frac": xops / (bkm * 1e-3) / PEAK_FP32, "ops_per_launch": xops,
+                                            "pair_terms_per_launch": apairs, "pair_terms_evaluated": xnear,
+                                            "all_pairs_equivalent_tflops": aops / (bkm * 1e-3) / 1e12}}
     log("fwd+bwd: %.3f ms/rollout (adjoint kernel %.3f ms)" % (fbms, bms / max(bl, 1)))
 
     observation(out, scene, ds, dev, traj2, reps)
@@ -469,6 +506,10 @@ def fwd_bwd_config3(out, dev, reps=3):
 
     res = {"unit": "rollout scenario-steps/s",
            "workload": "512 scenarios x 128 objects (8 controlled), 30000 road points, 80 steps, checkpoint every 10"}
+    tr = wm.State.empty((T, sc.total_objects), dev)
+    wm.rollout(ds.batch, ds.init, ds.act_seq, ds.log_seq, None, T, sc.dt, ds.batch.workspace(T, 0), traj=tr)
+    xops, xnear, _ = adjoint_executed_ops(ds.batch.obj_off, ds.act_seq.controlled, ds.init, ds.log_seq, tr, T)
+    del tr
     for key, met in (("full_metrics", fmet), ("loss_only", None)):
         fb(met)
         torch.cuda.synchronize()
@@ -487,7 +528,9 @@ def fwd_bwd_config3(out, dev, reps=3):
         aops, _ = adjoint_ops(sc, sc.controlled)
         res[key] = {"value": S * T / (ms * 1e-3), "agent_steps_per_s": sc.total_objects * T / (ms * 1e-3),
                     "ms_per_rollout": ms, "forward_kernel_ms": fms / max(fl, 1), "backward_kernel_ms": bkm,
-                    "backward_tflops": aops / (bkm * 1e-3) / 1e12, "backward_frac": aops / (bkm * 1e-3) / PEAK_FP32}
+                    "backward_tflops": xops / (bkm * 1e-3) / 1e12, "backward_frac": xops / (bkm * 1e-3) / PEAK_FP32,
+                    "pair_terms_evaluated": xnear,
+                    "all_pairs_equivalent_tflops": aops / (bkm * 1e-3) / 1e12}
         log("fwd+bwd (512 x 128, 8 controlled, %s): %.3f ms/rollout (forward kernel %.3f ms, adjoint %.3f ms)" % (
             key, ms, fms / max(fl, 1), bms / max(bl, 1)))
     res["value"] = res["full_metrics"]["value"]

@@ -13,7 +13,9 @@
 //      over every pair with a controlled member.  The pair terms do not
 //      depend on the adjoint, so all SB steps are done at once: a group of
 //      G lanes per (step, controlled object) splits the partners (j = lane,
-//      lane + G, ...) and sums them with a fixed shuffle tree;
+//      lane + G, ...) and sums them with a fixed shuffle tree.  A lane first
+//      marks the partners close enough for a non-zero term (a distance
+//      bound), then evaluates only those, in the same ascending order;
 //   3. one thread per controlled object runs the reverse recursion over the
 //      SB steps: the log-divergence term 2 (p - p_log), then back through the
 //      bicycle step, with the object's adjoint held in registers.  Its
@@ -35,6 +37,12 @@ constexpr int kBwdThreads = 1024;
 constexpr size_t kBwdStageBudget = 112 * 1024;   // LDS for the SB-step blocks
 constexpr int kBwdRec = 12;                       // recursion inputs per (step, controlled object)
 static_assert(kBwdRec % 4 == 0, "the recursion inputs are read as float4");
+// Pair terms whose margin is below -kCullGap are skipped: there -m / kSoftScale
+// exceeds 128 / log2(e), the FP32 exponential of the sigmoid overflows to
+// infinity and the term is exactly zero.
+constexpr float kCullGap = 9.0f;
+static_assert(kCullGap / kSoftScale * 1.4426950f > 129.0f, "skipped terms overflow the exponential");
+static_assert(WM_MAX_OBJECTS <= 64 * 32, "a lane's partners fit in one 32-bit mask");
 constexpr size_t kBwdStepBytes = 16 + 8 + 3 * 4 + kBwdRec * 4;   // LDS per step and object
 static_assert(WM_MAX_OBJECTS <= kBwdThreads, "one thread per controlled object");
 
@@ -230,22 +238,27 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                         ty = ok ? dm * uy : 0.f;
                         tt = ok ? dm * ut : 0.f;
                     };
-                    int j = gl;
-                    for (; j + 3 * G < N; j += 4 * G) {
-                        float tx[4], ty[4], tt[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            term(j + e * G, tx[e], ty[e], tt[e]);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            gx += tx[e];
-                            gy += ty[e];
-                            gt += tt[e];
-                        }
+                    // partners that may have a non-zero term: the margin is
+                    // at most r_i + r_j - d / sqrt(2) (r <= half length +
+                    // half width), and below -kCullGap the exponential above
+                    // overflows, so the term is exactly +-0
+                    const float ri = hi.x + hi.y;
+                    uint32_t near = 0;   // bit e: partner gl + e G
+                    for (int e = 0, j = gl; j < N; ++e, j += G) {
+                        const float4 pj = row4[j];
+                        const float2 hj = row2[j];
+                        const float dx = pj.x - pi.x, dy = pj.y - pi.y;
+                        const float rs = ri + hj.x + hj.y + kCullGap;
+                        if (__builtin_fmaf(dy, dy, dx * dx) <= 2.0f * rs * rs)
+                            near |= 1u << e;
                     }
-                    for (; j < N; j += G) {
+                    // their terms in ascending order: the sums equal those
+                    // over every partner (adding +-0 changes no sum)
+                    while (near) {
+                        const int e = __builtin_ctz(near);
+                        near &= near - 1u;
                         float ax, ay, at;
-                        term(j, ax, ay, at);
+                        term(gl + e * G, ax, ay, at);
                         gx += ax;
                         gy += ay;
                         gt += at;
