@@ -96,10 +96,21 @@ __global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict_
 // ---------------------------------------------------------------------------
 // Work units of the persistent rollout: scenario s is cut into
 // ceil(N_s / U) slices of U objects.  Unit ids are scenario-major
-// (uoff[s] + slice); the queue holds them in descending cost order
-// (cost = slice objects x padded road edges), a longest-first schedule.
-// Also resets the queue counter.  One block of 1024 threads.
+// (uoff[s] + slice); the queue holds them in descending cost order, a
+// longest-first schedule.  Also resets the queue counter.  One block of 1024
+// threads.
 // ---------------------------------------------------------------------------
+// Estimated cycles of one step of a unit of n objects in a scenario of N
+// objects and ep padded road edges (times 2): the off-road scan runs at a
+// granularity of 16 objects per wave (64 lanes, 4 corners each) at about 2.5
+// instructions per corner and edge, the pair tests at about 1 cycle per pair,
+// the candidate rescans at about 100 per object, plus a fixed part for the
+// barriers.  Only the order of the units depends on it.
+__device__ __forceinline__ unsigned long long unit_cost(int n, int N, unsigned long long ep)
+{
+    return 5ull * (unsigned long long)((n + 15) / 16) * ep + 2ull * (unsigned long long)n * N + 200ull * n + 8000ull;
+}
+
 __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict__ obj_off,
                                                       const int32_t *__restrict__ ecount, int S, int U,
                                                       int32_t *__restrict__ uoff, int2 *__restrict__ units,
@@ -152,7 +163,7 @@ __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict_
         const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
                                              : (unsigned long long)kChunk;
         for (int sl = 0; sl * U < N; ++sl) {
-            const unsigned long long c = (unsigned long long)min(U, N - sl * U) * ep;
+            const unsigned long long c = unit_cost(min(U, N - sl * U), N, ep);
             atomicMax(&maxcost, c);
         }
     }
@@ -163,7 +174,7 @@ __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict_
         const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
                                              : (unsigned long long)kChunk;
         for (int sl = 0; sl * U < N; ++sl) {
-            const unsigned long long c = (unsigned long long)min(U, N - sl * U) * ep;
+            const unsigned long long c = unit_cost(min(U, N - sl * U), N, ep);
             const int b = (int)((c * (NB - 1)) / mc);
             atomicAdd(&start[b], 1);
         }
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict_
         const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
                                              : (unsigned long long)kChunk;
         for (int sl = 0; sl * U < N; ++sl) {
-            const unsigned long long c = (unsigned long long)min(U, N - sl * U) * ep;
+            const unsigned long long c = unit_cost(min(U, N - sl * U), N, ep);
             const int b = (int)((c * (NB - 1)) / mc);
             const int pos = atomicAdd(&start[b], 1);
             units[pos] = make_int2(s, sl);
