@@ -100,15 +100,15 @@ __global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict_
 // longest-first schedule.  Also resets the queue counter.  One block of 1024
 // threads.
 // ---------------------------------------------------------------------------
-// Estimated cycles of one step of a unit of n objects in a scenario of N
-// objects and ep padded road edges (times 2): the off-road scan runs at a
-// granularity of 16 objects per wave (64 lanes, 4 corners each) at about 2.5
-// instructions per corner and edge, the pair tests at about 1 cycle per pair,
-// the candidate rescans at about 100 per object, plus a fixed part for the
-// barriers.  Only the order of the units depends on it.
-__device__ __forceinline__ unsigned long long unit_cost(int n, int N, unsigned long long ep)
+// Estimated cycles of one step of a unit of n objects with ep padded road
+// edges (times 2): the off-road scan runs at a granularity of 16 objects per
+// wave (64 lanes, 4 corners each) at about 2.5 instructions per corner and
+// edge, the candidate rescans at about 100 per object, plus a fixed part for
+// the barriers.  Only the order of the units depends on it; a term for the
+// pair tests (n x N) ordered the ragged batch measurably worse.
+__device__ __forceinline__ unsigned long long unit_cost(int n, unsigned long long ep)
 {
-    return 5ull * (unsigned long long)((n + 15) / 16) * ep + 2ull * (unsigned long long)n * N + 200ull * n + 8000ull;
+    return 5ull * (unsigned long long)((n + 15) / 16) * ep + 200ull * n + 8000ull;
 }
 
 __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict__ obj_off,
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict_
         const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
                                              : (unsigned long long)kChunk;
         for (int sl = 0; sl * U < N; ++sl) {
-            const unsigned long long c = unit_cost(min(U, N - sl * U), N, ep);
+            const unsigned long long c = unit_cost(min(U, N - sl * U), ep);
             atomicMax(&maxcost, c);
         }
     }
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict_
         const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
                                              : (unsigned long long)kChunk;
         for (int sl = 0; sl * U < N; ++sl) {
-            const unsigned long long c = unit_cost(min(U, N - sl * U), N, ep);
+            const unsigned long long c = unit_cost(min(U, N - sl * U), ep);
             const int b = (int)((c * (NB - 1)) / mc);
             atomicAdd(&start[b], 1);
         }
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict_
         const unsigned long long ep = ecount ? (unsigned long long)((ecount[s] + kChunk - 1) / kChunk * kChunk + kChunk)
                                              : (unsigned long long)kChunk;
         for (int sl = 0; sl * U < N; ++sl) {
-            const unsigned long long c = unit_cost(min(U, N - sl * U), N, ep);
+            const unsigned long long c = unit_cost(min(U, N - sl * U), ep);
             const int b = (int)((c * (NB - 1)) / mc);
             const int pos = atomicAdd(&start[b], 1);
             units[pos] = make_int2(s, sl);
