@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune", type=str, default=None, help="unit_objects,edge_splits (skips the autotuner)")
     ap.add_argument("--cpu-sample", type=int, default=8, help="scenarios of the oracle sample")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint of config 1 (every object controlled), for profiling it")
     ap.add_argument("--observe-only", action="store_true",
                     help="only time the observation of config 1 (one row, then the 80 logged rows) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -199,6 +201,9 @@ def main():
 
     dev = torch.device("cuda:0")
     wm.lib()
+    if args.adjoint_only:
+        print(json.dumps(adjoint_only(dev)), flush=True)
+        return
     t = time.perf_counter()
     scene = synth.make_scene(1)
     ds = wm.upload(scene, dev)
@@ -535,6 +540,44 @@ def fwd_bwd_config3(out, dev, reps=3):
             key, ms, fms / max(fl, 1), bms / max(bl, 1)))
     res["value"] = res["full_metrics"]["value"]
     out["fwd_bwd_config3"] = res
+
+
+def adjoint_only(dev, reps=3):
+    """The adjoint alone, for profiling it: config 1 with every object
+    controlled, the forward with the loss and checkpoints only (no road
+    graph), then the adjoint; its kernel time and executed work."""
+    import torch
+    from paper_2310_08710_amd import synth, wm
+    sc = synth.make_scene(1)
+    ds = wm.upload(sc, dev)
+    T, n = sc.steps, sc.total_objects
+    ctrl = torch.ones_like(ds.act_seq.controlled)
+    a = ds.act_seq.accel.clone().requires_grad_(True)
+    k = ds.act_seq.curvature.clone().requires_grad_(True)
+
+    def fb():
+        a.grad = None
+        k.grad = None
+        L = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ctrl, ds.log_seq, None, T, sc.dt, 10, None)
+        L.sum().backward()
+
+    fb()
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_BACKWARD)
+    for _ in range(reps):
+        fb()
+    torch.cuda.synchronize()
+    bms, bl = wm.profile_collect(wm.PROF_BACKWARD)
+    wm.profile_enable(False)
+    bkm = bms / max(bl, 1)
+    tr = wm.State.empty((T, n), dev)
+    wm.rollout(ds.batch, ds.init, wm.Action(ds.act_seq.accel, ds.act_seq.curvature, ctrl), ds.log_seq, None, T,
+               sc.dt, ds.batch.workspace(T, 0), traj=tr)
+    xops, xnear, tested = adjoint_executed_ops(ds.batch.obj_off, ctrl, ds.init, ds.log_seq, tr, T)
+    return {"workload": "adjoint of config 1, every object controlled, loss only, checkpoint every 10",
+            "backward_kernel_ms": bkm, "launches": bl, "ops_per_launch": xops, "pair_terms_evaluated": xnear,
+            "pair_terms": tested, "tflops": xops / (bkm * 1e-3) / 1e12}
 
 
 def idm(out, scene, ds, dev, tune):
