@@ -46,6 +46,13 @@ static_assert(WM_MAX_OBJECTS <= 64 * 32, "a lane's partners fit in one 32-bit ma
 constexpr size_t kBwdStepBytes = 16 + 8 + 3 * 4 + kBwdRec * 4;   // LDS per step and object
 static_assert(WM_MAX_OBJECTS <= kBwdThreads, "one thread per controlled object");
 
+// Byte offset of the per-wave pair lists in the adjoint's LDS: after the
+// step blocks, the controlled indices and the object kinds.
+__host__ __device__ constexpr size_t backward_wave_offset(int maxN, int SB)
+{
+    return ((size_t)SB * maxN * kBwdStepBytes + (size_t)maxN * 5 + 15) / 16 * 16;
+}
+
 __device__ __forceinline__ void store_state(float *row, long n, long g, float x, float y, float yaw, float vx, float vy)
 {
     row[g] = x;
@@ -70,6 +77,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
     float *part = (float *)(st2 + SB * maxN);
     int *cidx = (int *)(part + 3 * SB * maxN);
     uint8_t *kind = (uint8_t *)(cidx + maxN);
+    // per wave: the list of marked pairs being evaluated and their terms
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float4 *wres = (float4 *)(smem + backward_wave_offset(maxN, SB)) + 64 * wv;
+    int *wslot = (int *)(smem + backward_wave_offset(maxN, SB) + (size_t)kBwdThreads / 64 * 64 * 16) + 64 * wv;
     __shared__ int s_nc;
 
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -211,58 +222,80 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                 float gx = 0.f, gy = 0.f, gt = 0.f;
                 const int grp = u / G, gl = u - grp * G;
                 const int tb = grp / max(NC, 1), qq = grp - tb * NC;
+                const int i = u < items ? cidx[qq] : 0;
+                const int rb = u < items ? tb * maxN : 0;   // the step's row
+                // partners that may have a non-zero term: the margin is at most
+                // r_i + r_j - d / sqrt(2) (r <= half length + half width), and
+                // below -kCullGap the exponential of the term overflows, so the
+                // term is exactly +-0
+                uint32_t near = 0;   // bit e: partner gl + e G
                 if (u < items) {
-                    const int i = cidx[qq];
-                    const float4 pi = st4[tb * maxN + i];
-                    const float2 hi = st2[tb * maxN + i];
-                    const Box bi{pi.x, pi.y, pi.z, pi.w, hi.x, hi.y};
-                    const float4 *row4 = st4 + tb * maxN;
-                    const float2 *row2 = st2 + tb * maxN;
-                    // the partners j = gl, gl + G, ... in ascending order, four
-                    // per iteration; a term of j == i or of an invalid j is 0
-                    auto term = [&](int j, float &tx, float &ty, float &tt) {
-                        const float4 pj = row4[j];
-                        const float2 hj = row2[j];
-                        const Box bj{pj.x, pj.y, pj.z, pj.w, hj.x, hj.y};
-                        float ux, uy, ut;
-                        // the pair's margin with the lower index first, as in the forward
-                        const float m = i < j ? sat_margin_grad_one(bi, bj, false, ux, uy, ut)
-                                              : sat_margin_grad_one(bj, bi, true, ux, uy, ut);
-                        // the sigmoid's derivative only scales a gradient term:
-                        // the hardware exponential and reciprocal (about 1 ulp)
-                        const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-m * (1.0f / kSoftScale)));
-                        const float dm = sg * (1.0f - sg) * (1.0f / kSoftScale);
-                        // selects, not products: an invalid object's values may be anything
-                        const bool ok = j != i && hj.x >= 0.f;
-                        tx = ok ? dm * ux : 0.f;
-                        ty = ok ? dm * uy : 0.f;
-                        tt = ok ? dm * ut : 0.f;
-                    };
-                    // partners that may have a non-zero term: the margin is
-                    // at most r_i + r_j - d / sqrt(2) (r <= half length +
-                    // half width), and below -kCullGap the exponential above
-                    // overflows, so the term is exactly +-0
+                    const float4 pi = st4[rb + i];
+                    const float2 hi = st2[rb + i];
                     const float ri = hi.x + hi.y;
-                    uint32_t near = 0;   // bit e: partner gl + e G
                     for (int e = 0, j = gl; j < N; ++e, j += G) {
-                        const float4 pj = row4[j];
-                        const float2 hj = row2[j];
+                        const float4 pj = st4[rb + j];
+                        const float2 hj = st2[rb + j];
                         const float dx = pj.x - pi.x, dy = pj.y - pi.y;
                         const float rs = ri + hj.x + hj.y + kCullGap;
                         if (__builtin_fmaf(dy, dy, dx * dx) <= 2.0f * rs * rs)
                             near |= 1u << e;
                     }
-                    // their terms in ascending order: the sums equal those
-                    // over every partner (adding +-0 changes no sum)
-                    while (near) {
-                        const int e = __builtin_ctz(near);
-                        near &= near - 1u;
-                        float ax, ay, at;
-                        term(gl + e * G, ax, ay, at);
-                        gx += ax;
-                        gy += ay;
-                        gt += at;
+                }
+                // The wave's marked pairs, lane-major and in ascending partner
+                // order within a lane, are evaluated 64 at a time, one per lane;
+                // each lane then adds its own terms in that order, so its sums
+                // equal those over every partner (adding +-0 changes no sum).
+                const int cnt = __popc(near);
+                int incl = cnt;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int v = __shfl_up(incl, d);
+                    if (lane >= d)
+                        incl += v;
+                }
+                const int excl = incl - cnt, total = __shfl(incl, 63);
+                uint32_t rem = near;   // marked partners not yet listed
+                int listed = 0, added = 0;
+                for (int base = 0; base < total; base += 64) {   // wave-uniform
+                    while (rem && excl + listed < base + 64) {
+                        wslot[excl + listed - base] = (lane << 8) | __builtin_ctz(rem);
+                        rem &= rem - 1u;
+                        ++listed;
                     }
+                    __builtin_amdgcn_wave_barrier();   // the list precedes its reads
+                    const bool has = base + lane < total;
+                    const int v = wslot[lane];
+                    const int src = has ? (v >> 8) & 63 : lane;
+                    const int oi = __shfl(i, src), orb = __shfl(rb, src), ogl = __shfl(gl, src);
+                    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (has) {
+                        const int j = ogl + (v & 31) * G;
+                        const float4 pi = st4[orb + oi], pj = st4[orb + j];
+                        const float2 hi = st2[orb + oi], hj = st2[orb + j];
+                        const Box bi{pi.x, pi.y, pi.z, pi.w, hi.x, hi.y};
+                        const Box bj{pj.x, pj.y, pj.z, pj.w, hj.x, hj.y};
+                        float ux, uy, ut;
+                        // the pair's margin with the lower index first, as in the forward
+                        const float m = oi < j ? sat_margin_grad_one(bi, bj, false, ux, uy, ut)
+                                               : sat_margin_grad_one(bj, bi, true, ux, uy, ut);
+                        // the sigmoid's derivative only scales a gradient term:
+                        // the hardware exponential and reciprocal (about 1 ulp)
+                        const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-m * (1.0f / kSoftScale)));
+                        const float dm = sg * (1.0f - sg) * (1.0f / kSoftScale);
+                        // selects, not products: an invalid object's values may be anything
+                        const bool ok = j != oi && hj.x >= 0.f;
+                        r = make_float4(ok ? dm * ux : 0.f, ok ? dm * uy : 0.f, ok ? dm * ut : 0.f, 0.f);
+                    }
+                    wres[lane] = r;
+                    __builtin_amdgcn_wave_barrier();   // the terms precede their reads
+                    while (added < cnt && excl + added < base + 64) {
+                        const float4 t = wres[excl + added - base];
+                        gx += t.x;
+                        gy += t.y;
+                        gt += t.z;
+                        ++added;
+                    }
+                    __builtin_amdgcn_wave_barrier();   // the reads precede the next batch's writes
                 }
                 for (int d = G >> 1; d > 0; d >>= 1) {   // fixed tree within the group
                     gx += __shfl_xor(gx, d);
@@ -327,7 +360,7 @@ int backward_block_steps(int maxN, int K)
 
 static size_t backward_lds(int maxN, int SB)
 {
-    return align_up((size_t)SB * maxN * kBwdStepBytes + (size_t)maxN * 5, 16);
+    return backward_wave_offset(maxN, SB) + (size_t)kBwdThreads / 64 * 64 * (16 + 4);
 }
 
 void launch_backward(const BackwardArgs &a, hipStream_t st)
