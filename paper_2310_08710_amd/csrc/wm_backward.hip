@@ -15,7 +15,8 @@
 //      G lanes per (step, controlled object) splits the partners (j = lane,
 //      lane + G, ...) and sums them with a fixed shuffle tree.  A lane first
 //      marks the partners close enough for a non-zero term (a distance
-//      bound), then evaluates only those, in the same ascending order;
+//      bound); the wave evaluates its marked pairs one per lane, and each
+//      lane adds its own terms in ascending partner order;
 //   3. one thread per controlled object runs the reverse recursion over the
 //      SB steps: the log-divergence term 2 (p - p_log), then back through the
 //      bicycle step, with the object's adjoint held in registers.  Its
