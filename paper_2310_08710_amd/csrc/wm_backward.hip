@@ -35,7 +35,7 @@
 namespace wm {
 
 constexpr int kBwdThreads = 1024;
-constexpr size_t kBwdStageBudget = 112 * 1024;   // LDS for the SB-step blocks
+constexpr size_t kBwdStageBudget = 128 * 1024;   // LDS for the SB-step blocks
 constexpr int kBwdRec = 12;                       // recursion inputs per (step, controlled object)
 static_assert(kBwdRec % 4 == 0, "the recursion inputs are read as float4");
 // Pair terms whose margin is below -kCullGap are skipped: there -m / kSoftScale
@@ -44,8 +44,11 @@ static_assert(kBwdRec % 4 == 0, "the recursion inputs are read as float4");
 constexpr float kCullGap = 9.0f;
 static_assert(kCullGap / kSoftScale * 1.4426950f > 129.0f, "skipped terms overflow the exponential");
 static_assert(WM_MAX_OBJECTS <= 64 * 32, "a lane's partners fit in one 32-bit mask");
-constexpr size_t kBwdStepBytes = 16 + 8 + 3 * 4 + kBwdRec * 4;   // LDS per step and object
+constexpr size_t kBwdStepBytes = 16 + 16 + 8 + 3 * 4 + kBwdRec * 4;   // LDS per step and object
 static_assert(WM_MAX_OBJECTS <= kBwdThreads, "one thread per controlled object");
+static_assert(kBwdStageBudget + (size_t)WM_MAX_OBJECTS * 5 + 16 + (size_t)kBwdThreads / 64 * 64 * (16 + 4) <=
+                  160 * 1024,
+              "the step blocks, indices, kinds and the per-wave pair lists fit in a CU's LDS");
 
 // Byte offset of the per-wave pair lists in the adjoint's LDS: after the
 // step blocks, the controlled indices and the object kinds.
@@ -67,13 +70,16 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int maxN = A.maxN, SB = A.SB;
-    // LDS: [SB][maxN] (x, y, cos, sin), the recursion's inputs [SB][maxN][12]
-    // per controlled slot (16-byte aligned), [SB][maxN] (half length or -1
-    // when invalid, half width), the pair-term sums [SB][maxN][3]; the
-    // controlled objects' indices; per object 2 (controlled and valid), 1
-    // (controlled, invalid) or 0 (from the log)
+    // LDS: [SB][maxN] (x, y, cos, sin), [SB][maxN] (x, y, reach, 0) for the
+    // distance bound (reach: half length + half width + kCullGap), the
+    // recursion's inputs [SB][maxN][12] per controlled slot (16-byte
+    // aligned), [SB][maxN] (half length or -1 when invalid, half width), the
+    // pair-term sums [SB][maxN][3]; the controlled objects' indices; per
+    // object 2 (controlled and valid), 1 (controlled, invalid) or 0 (from the
+    // log)
     float4 *st4 = (float4 *)smem;
-    float *rec = (float *)(st4 + SB * maxN);
+    float4 *tst = st4 + SB * maxN;
+    float *rec = (float *)(tst + SB * maxN);
     float2 *st2 = (float2 *)(rec + kBwdRec * SB * maxN);
     float *part = (float *)(st2 + SB * maxN);
     int *cidx = (int *)(part + 3 * SB * maxN);
@@ -192,8 +198,10 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                 float sn, cs;
                 sincosf(yaw, &sn, &cs);
                 const int at = tb * maxN + i;
+                const float hl = v ? 0.5f * len : -1.f, hw = 0.5f * wid;
                 st4[at] = make_float4(x, y, cs, sn);
-                st2[at] = make_float2(v ? 0.5f * len : -1.f, 0.5f * wid);
+                tst[at] = make_float4(x, y, hl + hw + kCullGap, 0.f);
+                st2[at] = make_float2(hl, hw);
             }
             // the recursion's inputs, which do not depend on the adjoint: the
             // log position at t and the factors of the bicycle step's
@@ -231,14 +239,12 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                 // term is exactly +-0
                 uint32_t near = 0;   // bit e: partner gl + e G
                 if (u < items) {
-                    const float4 pi = st4[rb + i];
-                    const float2 hi = st2[rb + i];
-                    const float ri = hi.x + hi.y;
+                    const float4 pi = tst[rb + i];
+                    const float ri = pi.z - kCullGap;   // half length + half width (+- rounding)
                     for (int e = 0, j = gl; j < N; ++e, j += G) {
-                        const float4 pj = st4[rb + j];
-                        const float2 hj = st2[rb + j];
+                        const float4 pj = tst[rb + j];
                         const float dx = pj.x - pi.x, dy = pj.y - pi.y;
-                        const float rs = ri + hj.x + hj.y + kCullGap;
+                        const float rs = ri + pj.z;
                         if (__builtin_fmaf(dy, dy, dx * dx) <= 2.0f * rs * rs)
                             near |= 1u << e;
                     }
