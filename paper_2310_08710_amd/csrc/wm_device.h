@@ -157,19 +157,10 @@ __device__ __forceinline__ void idm_interp(const float4 *__restrict__ path, int 
     yaw = __builtin_fmaf(lam, wrap_angle(b.z - a.z), a.z);
 }
 
-// The pose of an IDM agent at its path progress s, with lo its segment
-// index from an earlier, not larger progress (1 at the start): the progress
-// never decreases, so the first path point past s lies at or after lo, and
-// a forward scan from there finds the same segment as a search of the whole
-// path, usually in a step or two.  Updates lo.
-__device__ __forceinline__ void idm_pose_from(const float4 *__restrict__ path, int T, float s, int &lo, float &x,
-                                              float &y, float &yaw)
+__device__ __forceinline__ void idm_pose(const float4 *__restrict__ path, int T, float s, float &x, float &y,
+                                         float &yaw)
 {
-    int k = lo;
-    while (k <= T && path[k].w <= s)
-        ++k;
-    lo = k;
-    idm_interp(path, T, k, s, x, y, yaw);
+    idm_interp(path, T, idm_segment([&](int k) { return path[k].w; }, T, s), s, x, y, yaw);
 }
 
 // IDM acceleration for speed v; `lead` selects the interaction term with gap

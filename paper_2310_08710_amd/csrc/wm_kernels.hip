@@ -748,9 +748,8 @@ __device__ __forceinline__ int wave_min(int v)
 // pose-major order, so the first pass with an overlap holds the lead (a
 // wave minimum of pose * 2048 + index).  wscr: the off-road scratch, unused
 // at this point of the step.  Contains three block barriers.
-__device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, int o0, int N, const float *sig, int *slo,
-                                          float *ia, int *lk, const uint8_t *agent, float *pc, uint32_t *mask,
-                                          float *wscr)
+__device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, int o0, int N, const float *sig, float *ia,
+                                          int *lk, const uint8_t *agent, float *pc, uint32_t *mask, float *wscr)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6, nw = nthr >> 6;
@@ -762,7 +761,7 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
         rad[i] = 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i]));
         if (use_mask && agent[i]) {
             float yaw;
-            idm_pose_from(A.idmP + (long)(o0 + i) * (A.T + 1), A.T, sig[i], slo[i], pc[2 * i], pc[2 * i + 1], yaw);
+            idm_pose(A.idmP + (long)(o0 + i) * (A.T + 1), A.T, sig[i], pc[2 * i], pc[2 * i + 1], yaw);
         }
     }
     __syncthreads();
@@ -888,7 +887,7 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
 // Advance IDM agent i (global g) with acceleration a along its path; the
 // next state's length, width and valid come from log row `row`.
 __device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int i, long g, long row, float *sig,
-                                         int *slo, float a)
+                                         float a)
 {
     const float dt = A.dt;
     const float v = sqrtf(__builtin_fmaf(L.vy[i], L.vy[i], L.vx[i] * L.vx[i]));
@@ -908,7 +907,7 @@ __device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int
         sig[i] += adv;
     }
     float x, y, yaw, sn, cs;
-    idm_pose_from(path, A.T, sig[i], slo[i], x, y, yaw);
+    idm_pose(path, A.T, sig[i], x, y, yaw);
     sincosf(yaw, &sn, &cs);
     L.x[i] = x;
     L.y[i] = y;
@@ -964,8 +963,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     int *lk = (int *)(ia + A.maxN);      // IDM: lead key m * 2048 + j
     uint8_t *agent = (uint8_t *)(lk + A.maxN);
     float *pc = (float *)(agent + align_up((size_t)A.maxN, 16));   // IDM: pose at sig (x, y)
-    int *slo = (int *)(pc + 2 * A.maxN);                              // IDM: path segment at sig
-    uint32_t *mask = (uint32_t *)(slo + A.maxN);                      // IDM: candidate bit masks
+    uint32_t *mask = (uint32_t *)(pc + 2 * A.maxN);                   // IDM: candidate bit masks
     __shared__ int s_unit;
     const int tid = threadIdx.x;
     const long n = A.n;
@@ -993,7 +991,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             L.ctrl[i] = A.act.controlled[o0 + i];
             if (A.has_idm) {
                 sig[i] = 0.f;
-                slo[i] = 1;
                 agent[i] = A.idmA[o0 + i];
             }
         }
@@ -1005,13 +1002,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int t = 1; t <= A.T; ++t) {
             const long row = (long)t * n, arow = (long)(t - 1) * n;
             if (A.has_idm)
-                idm_leads(A, L, o0, N, sig, slo, ia, lk, agent, pc, mask, (float *)C.stage);
+                idm_leads(A, L, o0, N, sig, ia, lk, agent, pc, mask, (float *)C.stage);
             for (int i = tid; i < N; i += nthr) {
                 const long g = o0 + i;
                 const float pvx = L.vx[i], pvy = L.vy[i], pyaw = L.yaw[i];
                 const bool pvalid = L.valid[i];
                 if (!L.ctrl[i] && A.has_idm && agent[i]) {
-                    idm_move(A, L, i, g, row, sig, slo, ia[i]);
+                    idm_move(A, L, i, g, row, sig, ia[i]);
                 } else if (!L.ctrl[i]) {
                     load_object(L, i, A.log, row + g);
                 } else if (L.valid[i]) {
@@ -1168,7 +1165,7 @@ void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
 size_t rollout_lds_bytes(int maxN, int G, int CW)
 {
     const int nthr = 64 * CW * G;
-    const size_t idm = (size_t)maxN * 12 + align_up((size_t)maxN, 16) + (size_t)maxN * 12 +
+    const size_t idm = (size_t)maxN * 12 + align_up((size_t)maxN, 16) + (size_t)maxN * 8 +
                        (maxN <= kIdmMaskMaxN ? (size_t)maxN * ((maxN + 31) / 32) * 4 : 0);
     return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up(idm, 16);
 }
