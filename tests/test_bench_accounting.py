@@ -1,0 +1,62 @@
+"""The bench's count of the adjoint's evaluated pair terms (the work its
+roofline figure is taken on), on small hand-placed scenes on the CPU: every
+controlled object counts its pair with itself, partners beyond the distance
+bound do not count, partners within it do."""
+import math
+import os
+import sys
+
+import numpy as np
+import torch
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+from paper_2310_08710_amd import wm  # noqa: E402
+
+
+def _scene(xs, ys, T, length=4.0, width=2.0):
+    """One scenario; the objects stand still at (xs, ys) for T + 1 rows."""
+    n = len(xs)
+    rows = T + 1
+    x = torch.tensor(np.tile(np.asarray(xs, np.float32), (rows, 1)))
+    y = torch.tensor(np.tile(np.asarray(ys, np.float32), (rows, 1)))
+    z = torch.zeros((rows, n))
+    ln = torch.full((rows, n), length)
+    wd = torch.full((rows, n), width)
+    log = wm.State(x, y, z.clone(), z.clone(), z.clone(), ln, wd, torch.ones((rows, n), dtype=torch.uint8))
+    init = wm.State(*[getattr(log, f)[0].clone() for f in wm.STATE_FIELDS], log.valid[0].clone())
+    traj = wm.State(*[getattr(log, f)[1:].clone() for f in wm.STATE_FIELDS], log.valid[1:].clone())
+    off = torch.tensor([0, n], dtype=torch.int32)
+    return off, init, log, traj
+
+
+def test_far_apart_objects_count_only_themselves():
+    T = 5
+    off, init, log, traj = _scene([0.0, 100.0, 200.0], [0.0, 0.0, 0.0], T)
+    ctrl = torch.tensor([1, 1, 0], dtype=torch.uint8)
+    ops, near, tested = bench.adjoint_executed_ops(off, ctrl, init, log, traj, T)
+    assert near == T * 2                  # each controlled object with itself
+    assert tested == T * 2 * 2            # partners other than itself
+    assert ops == T * (bench.ADJ_OPS_PER_TEST * 2 * 3 + bench.ADJ_OPS_PER_OBJECT * 2) + bench.ADJ_OPS_PER_PAIR * near
+
+
+def test_bound_edge():
+    # reach r = half length + half width = 3 m each; the bound counts a pair
+    # when d <= sqrt(2) (r_i + r_j + gap)
+    T = 3
+    edge = math.sqrt(2.0) * (3.0 + 3.0 + bench.ADJ_CULL_GAP)
+    off, init, log, traj = _scene([0.0, edge - 0.05, -(edge + 0.05)], [0.0, 0.0, 0.0], T)
+    ctrl = torch.tensor([1, 0, 0], dtype=torch.uint8)
+    _, near, _ = bench.adjoint_executed_ops(off, ctrl, init, log, traj, T)
+    assert near == T * 2                  # itself and the object just inside
+
+
+def test_uncontrolled_objects_come_from_the_log():
+    # the controlled object's trajectory moves it next to object 1 after the
+    # first step; the log keeps it far away
+    T = 4
+    off, init, log, traj = _scene([0.0, 500.0], [0.0, 0.0], T)
+    traj.x[1:, 0] = 495.0
+    ctrl = torch.tensor([1, 0], dtype=torch.uint8)
+    _, near, _ = bench.adjoint_executed_ops(off, ctrl, init, log, traj, T)
+    assert near == T + (T - 1)
