@@ -76,7 +76,7 @@ def adjoint_executed_ops(obj_off, controlled, init, log_seq, traj, T):
     """Ops one adjoint launch executes, and the pair terms it evaluates: every
     (controlled object, partner) pair is tested at every step, and the terms
     within the bound sqrt(2) (r_i + r_j + ADJ_CULL_GAP) (r = half length + half
-    width; the pair of an object with itself included) are evaluated.  States:
+    width; an object is never its own partner) are evaluated.  States:
     controlled objects from the trajectory, the others from the log.  Scenes
     of uniform object count."""
     import torch
@@ -95,6 +95,7 @@ def adjoint_executed_ops(obj_off, controlled, init, log_seq, traj, T):
         d2 = (x[:, :, None] - x[:, None, :]) ** 2 + (y[:, :, None] - y[:, None, :]) ** 2
         rs = r[:, :, None] + r[:, None, :] + ADJ_CULL_GAP
         m = (d2 <= 2.0 * rs * rs) & ctrl.view(S, N)[:, :, None]
+        m &= ~torch.eye(N, dtype=torch.bool, device=m.device)[None]
         near += int(m.sum())
     ops = T * (ADJ_OPS_PER_TEST * nc * N + ADJ_OPS_PER_OBJECT * nc) + ADJ_OPS_PER_PAIR * near
     return float(ops), float(near), float(T * nc * (N - 1))

@@ -149,6 +149,11 @@ typedef struct wm_tuning {
  * checkpoints).  Returns 0 if the batch is invalid. */
 size_t wm_workspace_bytes(const wm_batch *batch, int32_t T, int32_t ckpt_every);
 
+/* The same number under the name of the rollout's workspace query: bytes of
+ * workspace for wm_rollout / wm_rollout_backward with this T and checkpoint
+ * interval (every other call on the batch fits in it too). */
+size_t wm_rollout_workspace_bytes(const wm_batch *batch, int32_t T, int32_t ckpt_every);
+
 /* One simulator step (Sec. 4.1 step(state, action); dynamics App. A.1
  * bicycle forward).  For every object:
  *   controlled & valid   : bicycle forward with (accel, curvature)

@@ -211,6 +211,11 @@ size_t wm_workspace_bytes(const wm_batch *batch, int32_t T, int32_t ckpt_every)
     return workspace_bytes(batch, T, ckpt_every);
 }
 
+size_t wm_rollout_workspace_bytes(const wm_batch *batch, int32_t T, int32_t ckpt_every)
+{
+    return wm_workspace_bytes(batch, T, ckpt_every);
+}
+
 const char *wm_error_string(int code)
 {
     switch (code) {

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                         const float4 pj = tst[rb + j];
                         const float dx = pj.x - pi.x, dy = pj.y - pi.y;
                         const float rs = ri + pj.z;
-                        if (__builtin_fmaf(dy, dy, dx * dx) <= 2.0f * rs * rs)
+                        // the object itself is never a partner
+                        if (j != i && __builtin_fmaf(dy, dy, dx * dx) <= 2.0f * rs * rs)
                             near |= 1u << e;
                     }
                 }
@@ -289,8 +290,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_rollout_backward(BackwardArgs A
                         // the hardware exponential and reciprocal (about 1 ulp)
                         const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-m * (1.0f / kSoftScale)));
                         const float dm = sg * (1.0f - sg) * (1.0f / kSoftScale);
-                        // selects, not products: an invalid object's values may be anything
-                        const bool ok = j != oi && hj.x >= 0.f;
+                        // selects, not products: an invalid object's values may be
+                        // anything (the bound never marks the object itself)
+                        const bool ok = hj.x >= 0.f;
                         r = make_float4(ok ? dm * ux : 0.f, ok ? dm * uy : 0.f, ok ? dm * ut : 0.f, 0.f);
                     }
                     wres[lane] = r;

@@ -1215,6 +1215,11 @@ int rollout_grid(int G, int CW, int maxN, int n_units_bound)
 void launch_rollout(const RollArgs &a, int grid, hipStream_t st)
 {
     const size_t lds = rollout_lds_bytes(a.maxN, a.G, a.CW);
+    // set on every launch: the limit is per function, and an earlier launch
+    // of another shape may have lowered it (a host-side call, not a stream
+    // operation, so graph capture is unaffected)
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_rollout, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_rollout, dim3(grid), dim3(64 * a.CW * a.G), lds, st, a);
 }
 

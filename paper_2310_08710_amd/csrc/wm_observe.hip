@@ -284,7 +284,11 @@ __device__ __forceinline__ bool topk_select(const Src &src, int kk, const TopkLd
         // lowest indices win.  Index order is j = tid + 1024 r: round r
         // first, then wave, then lane; wave counts per round go through LDS.
         const int lane = tid & 63, wv = tid >> 6;
-        int *wc = L.hist + kBins;   // [round][wave]; this histogram copy is no longer needed
+        // [round][wave] counts in the boundary-set array, which this path
+        // never fills (its members are marked in eqm instead)
+        static_assert(kObsKeys * (kObsThreads / 64) * sizeof(int) <= kCandCap * sizeof(uint64_t),
+                      "per-round wave counts fit in the boundary-set array");
+        int *wc = (int *)L.cand;
         for (int r = 0; r < kObsKeys; ++r) {
             const int cnt = __popcll(__ballot((eqm >> r) & 1u));
             if (lane == 0)

@@ -88,6 +88,8 @@ def lib() -> C.CDLL:
         L = C.CDLL(LIB_PATH)
         L.wm_workspace_bytes.restype = C.c_size_t
         L.wm_workspace_bytes.argtypes = [C.POINTER(CBatch), C.c_int32, C.c_int32]
+        L.wm_rollout_workspace_bytes.restype = C.c_size_t
+        L.wm_rollout_workspace_bytes.argtypes = [C.POINTER(CBatch), C.c_int32, C.c_int32]
         L.wm_error_string.restype = C.c_char_p
         L.wm_error_string.argtypes = [C.c_int]
         L.wm_last_error_message.restype = C.c_char_p
@@ -140,6 +142,22 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else t.data_ptr()
 
 
+def _need(t: Optional[torch.Tensor], numel: int, dtype: torch.dtype, name: str, optional: bool = True):
+    """Raise ValueError unless t is a contiguous tensor of `dtype` with at least
+    `numel` elements (the library trusts device pointers, so a short tensor
+    would become an out-of-bounds device access).  None passes when optional."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError("%s is required" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ValueError("%s has %d elements, %d needed" % (name, t.numel(), numel))
+
+
 def _stream(stream=None):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -170,6 +188,8 @@ class Batch:
                    int(np.diff(rg_off).max()) if S else 0)
 
     def c(self) -> CBatch:
+        _need(self.obj_off, self.num_scenarios + 1, torch.int32, "batch.obj_off", False)
+        _need(self.rg_off, self.num_scenarios + 1, torch.int32, "batch.rg_off", False)
         return CBatch(self.num_scenarios, self.total_objects, self.total_rg_points, self.max_objects,
                       self.max_rg_points, self.obj_off.data_ptr(), self.rg_off.data_ptr())
 
@@ -194,11 +214,11 @@ class State:
     width: torch.Tensor
     valid: torch.Tensor
 
-    def c(self) -> CState:
-        for f in dataclasses.fields(self):
-            t = getattr(self, f.name)
-            if not t.is_contiguous():
-                raise ValueError("state field %s must be contiguous" % f.name)
+    def c(self, numel: int = 0, name: str = "state") -> CState:
+        """C view; every field must hold at least `numel` entries."""
+        for f in STATE_FIELDS:
+            _need(getattr(self, f), numel, torch.float32, "%s.%s" % (name, f), False)
+        _need(self.valid, numel, torch.uint8, name + ".valid", False)
         return CState(*[getattr(self, f).data_ptr() for f in STATE_FIELDS], self.valid.data_ptr())
 
     @classmethod
@@ -227,7 +247,12 @@ class Roadgraph:
     type: torch.Tensor
     valid: torch.Tensor
 
-    def c(self) -> CRoadgraph:
+    def c(self, numel: int = 0) -> CRoadgraph:
+        """C view; every field must hold at least `numel` points."""
+        for f in ("x", "y", "dir_x", "dir_y"):
+            _need(getattr(self, f), numel, torch.float32, "rg." + f, False)
+        _need(self.type, numel, torch.int8, "rg.type", False)
+        _need(self.valid, numel, torch.uint8, "rg.valid", False)
         return CRoadgraph(self.x.data_ptr(), self.y.data_ptr(), self.dir_x.data_ptr(), self.dir_y.data_ptr(),
                           self.type.data_ptr(), self.valid.data_ptr())
 
@@ -244,7 +269,11 @@ class Action:
     curvature: torch.Tensor
     controlled: torch.Tensor
 
-    def c(self) -> CAction:
+    def c(self, numel: int = 0, n: int = 0) -> CAction:
+        """C view; accel / curvature hold at least `numel` entries, controlled `n`."""
+        _need(self.accel, numel, torch.float32, "accel", False)
+        _need(self.curvature, numel, torch.float32, "curvature", False)
+        _need(self.controlled, n, torch.uint8, "controlled", False)
         return CAction(self.accel.data_ptr(), self.curvature.data_ptr(), self.controlled.data_ptr())
 
 
@@ -269,7 +298,11 @@ class Metrics:
     def row(self, t: int) -> "Metrics":
         return Metrics(*[None if getattr(self, f) is None else getattr(self, f)[t] for f in self.FIELDS])
 
-    def c(self) -> CMetrics:
+    def c(self, numel: int = 0) -> CMetrics:
+        """C view; every given member must hold at least `numel` entries."""
+        for f in self.FIELDS:
+            _need(getattr(self, f), numel, torch.uint8 if f in ("collision", "offroad", "infeasible") else
+                  torch.float32, "metrics." + f)
         return CMetrics(_ptr(self.collision), _ptr(self.offroad), _ptr(self.overlap_margin),
                         _ptr(self.offroad_margin), _ptr(self.log_div), _ptr(self.infeasible), _ptr(self.reward))
 
@@ -284,9 +317,10 @@ def _tune(t):
 # Entry points (same names as the C ABI)
 # ---------------------------------------------------------------------------
 def _step(fn, batch, cur, act, log_next, rg, dt, nxt, metrics, ws, stream):
-    b, c, a, l, n = batch.c(), cur.c(), act.c(), log_next.c(), nxt.c()
-    r = rg.c() if rg is not None else None
-    m = metrics.c() if metrics is not None else None
+    N = batch.total_objects
+    b, c, a, l, n = batch.c(), cur.c(N, "cur"), act.c(N, N), log_next.c(N, "log_next"), nxt.c(N, "next")
+    r = rg.c(batch.total_rg_points) if rg is not None else None
+    m = metrics.c(N) if metrics is not None else None
     _check(fn(C.byref(b), C.byref(c), C.byref(a), C.byref(l), C.byref(r) if r is not None else None, dt, C.byref(n),
               C.byref(m) if m is not None else None, _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream)))
 
@@ -298,7 +332,7 @@ def step(batch: Batch, cur: State, act: Action, log_next: State, rg: Optional[Ro
 
 def roadgraph_prepare(batch: Batch, rg: Roadgraph, ws: torch.Tensor, stream=None):
     """Compact the road edges into `ws` once for step_prepared()."""
-    b, r = batch.c(), rg.c()
+    b, r = batch.c(), rg.c(batch.total_rg_points)
     _check(lib().wm_roadgraph_prepare(C.byref(b), C.byref(r), ws.data_ptr(), ws.numel(), _stream(stream)))
 
 
@@ -310,48 +344,89 @@ def step_prepared(batch: Batch, cur: State, act: Action, log_next: State, rg: Op
 
 def inverse_action(batch: Batch, cur: State, nxt: State, dt: float, accel: torch.Tensor, curvature: torch.Tensor,
                    valid_out: Optional[torch.Tensor] = None, stream=None):
-    b, c, n = batch.c(), cur.c(), nxt.c()
+    N = batch.total_objects
+    b, c, n = batch.c(), cur.c(N, "cur"), nxt.c(N, "next")
+    _need(accel, N, torch.float32, "accel", False)
+    _need(curvature, N, torch.float32, "curvature", False)
+    _need(valid_out, N, torch.uint8, "valid_out")
     _check(lib().wm_inverse_action(C.byref(b), C.byref(c), C.byref(n), dt, accel.data_ptr(), curvature.data_ptr(),
                                    _ptr(valid_out), _stream(stream)))
 
 
 def step_delta(batch: Batch, cur: State, dx: torch.Tensor, dy: torch.Tensor, dyaw: torch.Tensor,
                controlled: torch.Tensor, log_next: State, dt: float, nxt: State, stream=None):
-    b, c, l, n = batch.c(), cur.c(), log_next.c(), nxt.c()
+    N = batch.total_objects
+    b, c, l, n = batch.c(), cur.c(N, "cur"), log_next.c(N, "log_next"), nxt.c(N, "next")
+    for t, nm in ((dx, "dx"), (dy, "dy"), (dyaw, "dyaw")):
+        _need(t, N, torch.float32, nm, False)
+    _need(controlled, N, torch.uint8, "controlled", False)
     a = CDeltaAction(dx.data_ptr(), dy.data_ptr(), dyaw.data_ptr(), controlled.data_ptr())
     _check(lib().wm_step_delta(C.byref(b), C.byref(c), C.byref(a), C.byref(l), dt, C.byref(n), _stream(stream)))
 
 
 def inverse_delta(batch: Batch, cur: State, nxt: State, dx: torch.Tensor, dy: torch.Tensor, dyaw: torch.Tensor,
                   valid_out: Optional[torch.Tensor] = None, stream=None):
-    b, c, n = batch.c(), cur.c(), nxt.c()
+    N = batch.total_objects
+    b, c, n = batch.c(), cur.c(N, "cur"), nxt.c(N, "next")
+    for t, nm in ((dx, "dx"), (dy, "dy"), (dyaw, "dyaw")):
+        _need(t, N, torch.float32, nm, False)
+    _need(valid_out, N, torch.uint8, "valid_out")
     _check(lib().wm_inverse_delta(C.byref(b), C.byref(c), C.byref(n), dx.data_ptr(), dy.data_ptr(), dyaw.data_ptr(),
                                   _ptr(valid_out), _stream(stream)))
 
 
 def discretize(values: torch.Tensor, lo: float, hi: float, bins: int, index: torch.Tensor,
                snapped: Optional[torch.Tensor] = None, stream=None):
+    _need(values, 0, torch.float32, "values", False)
+    _need(index, values.numel(), torch.int32, "index", False)
+    _need(snapped, values.numel(), torch.float32, "snapped")
     _check(lib().wm_discretize(values.data_ptr(), values.numel(), lo, hi, bins, index.data_ptr(), _ptr(snapped),
                                _stream(stream)))
 
 
 def overlap(batch: Batch, st: State, collision=None, max_margin=None, pair_off=None, margin=None, mask=None,
             stream=None):
-    b, s = batch.c(), st.c()
+    """Collision metric; with `margin` / `mask` also the per-scenario pair
+    matrices, whose total size is read back from pair_off[S] (a synchronizing
+    copy, so the matrix form is not for graph capture)."""
+    N = batch.total_objects
+    b, s = batch.c(), st.c(N)
+    _need(collision, N, torch.uint8, "collision")
+    _need(max_margin, N, torch.float32, "max_margin")
+    if margin is not None or mask is not None:
+        _need(pair_off, batch.num_scenarios + 1, torch.int64, "pair_off", False)
+        # the last block ends at pair_off[S] (host copy: a synchronizing read)
+        pairs = int(pair_off[batch.num_scenarios].item())
+        _need(margin, pairs, torch.float32, "margin")
+        _need(mask, pairs, torch.uint8, "mask")
     _check(lib().wm_overlap(C.byref(b), C.byref(s), _ptr(pair_off), _ptr(margin), _ptr(mask), _ptr(collision),
                             _ptr(max_margin), _stream(stream)))
 
 
 def offroad(batch: Batch, st: State, rg: Roadgraph, ws: torch.Tensor, offroad=None, margin=None, nearest=None,
             tune=None, stream=None):
-    b, s, r = batch.c(), st.c(), rg.c()
+    N = batch.total_objects
+    b, s, r = batch.c(), st.c(N), rg.c(batch.total_rg_points)
+    _need(offroad, N, torch.uint8, "offroad")
+    _need(margin, N, torch.float32, "margin")
+    _need(nearest, 4 * N, torch.int32, "nearest")
+    _need(ws, 0, torch.uint8, "ws", False)
     _check(lib().wm_offroad(C.byref(b), C.byref(s), C.byref(r), _ptr(offroad), _ptr(margin), _ptr(nearest),
                             _tune(tune), ws.data_ptr(), ws.numel(), _stream(stream)))
 
 
+def _observe_sizes(batch, T, ego, E, k, rg_idx, rg_feat, obj_feat):
+    slots = batch.num_scenarios * max(E, 0)
+    _need(ego, slots, torch.int32, "ego", False)
+    _need(rg_idx, T * slots * max(k, 0), torch.int32, "rg_idx", False)
+    _need(rg_feat, T * slots * max(k, 0) * 4, torch.float32, "rg_feat")
+    _need(obj_feat, T * slots * batch.max_objects * 8, torch.float32, "obj_feat")
+
+
 def observe(batch: Batch, st: State, rg: Roadgraph, ego: torch.Tensor, E: int, k: int, rg_idx: torch.Tensor,
             rg_feat=None, obj_feat=None, stream=None):
-    b, s, r = batch.c(), st.c(), rg.c()
+    b, s, r = batch.c(), st.c(batch.total_objects), rg.c(batch.total_rg_points)
+    _observe_sizes(batch, 1, ego, E, k, rg_idx, rg_feat, obj_feat)
     _check(lib().wm_observe(C.byref(b), C.byref(s), C.byref(r), ego.data_ptr(), E, k, rg_idx.data_ptr(),
                             _ptr(rg_feat), _ptr(obj_feat), _stream(stream)))
 
@@ -361,7 +436,8 @@ def observe_seq(batch: Batch, traj: State, T: int, rg: Roadgraph, ego: torch.Ten
                 stream=None):
     """Observation of every row of a [T, n] state sequence in one launch;
     outputs are [T, ...] with each row as in observe()."""
-    b, st, r = batch.c(), traj.c(), rg.c()
+    b, st, r = batch.c(), traj.c(T * batch.total_objects, "traj"), rg.c(batch.total_rg_points)
+    _observe_sizes(batch, T, ego, E, k, rg_idx, rg_feat, obj_feat)
     _check(lib().wm_observe_seq(C.byref(b), C.byref(st), T, C.byref(r), ego.data_ptr(), E, k, rg_idx.data_ptr(),
                                 _ptr(rg_feat), _ptr(obj_feat), _stream(stream)))
 
@@ -369,11 +445,14 @@ def observe_seq(batch: Batch, traj: State, T: int, rg: Roadgraph, ego: torch.Ten
 def rollout(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: Optional[Roadgraph], T: int, dt: float,
             ws: torch.Tensor, ckpt_every: int = 0, ckpt: Optional[State] = None, traj: Optional[State] = None,
             metrics: Optional[Metrics] = None, loss: Optional[torch.Tensor] = None, tune=None, stream=None):
-    b, i, a, l = batch.c(), init.c(), act_seq.c(), log_seq.c()
-    r = rg.c() if rg is not None else None
-    ck = ckpt.c() if ckpt is not None else None
-    tr = traj.c() if traj is not None else None
-    m = metrics.c() if metrics is not None else None
+    N = batch.total_objects
+    b, i, a, l = batch.c(), init.c(N, "init"), act_seq.c(T * N, N), log_seq.c((T + 1) * N, "log_seq")
+    r = rg.c(batch.total_rg_points) if rg is not None else None
+    ck = ckpt.c(-(-T // max(ckpt_every, 1)) * N, "ckpt") if ckpt is not None else None
+    tr = traj.c(T * N, "traj") if traj is not None else None
+    m = metrics.c(T * N) if metrics is not None else None
+    _need(loss, batch.num_scenarios, torch.float32, "loss")
+    _need(ws, 0, torch.uint8, "ws", False)
     _check(lib().wm_rollout(C.byref(b), C.byref(i), C.byref(a), C.byref(l), C.byref(r) if r is not None else None,
                             T, dt, ckpt_every, C.byref(ck) if ck is not None else None,
                             C.byref(tr) if tr is not None else None, C.byref(m) if m is not None else None,
@@ -389,10 +468,12 @@ def rollout_idm(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: 
     par.update(idm or {})
     p = CIdm(*[float(par[k]) for k in ("desired_speed", "min_gap", "time_headway", "max_accel", "comfort_decel",
                                        "exponent", "max_brake", "lookahead_step")], int(par["lookahead_poses"]))
-    b, i, a, l = batch.c(), init.c(), act_seq.c(), log_seq.c()
-    r = rg.c() if rg is not None else None
-    tr = traj.c() if traj is not None else None
-    m = metrics.c() if metrics is not None else None
+    N = batch.total_objects
+    b, i, a, l = batch.c(), init.c(N, "init"), act_seq.c(T * N, N), log_seq.c((T + 1) * N, "log_seq")
+    r = rg.c(batch.total_rg_points) if rg is not None else None
+    tr = traj.c(T * N, "traj") if traj is not None else None
+    m = metrics.c(T * N) if metrics is not None else None
+    _need(ws, 0, torch.uint8, "ws", False)
     _check(lib().wm_rollout_idm(C.byref(b), C.byref(i), C.byref(a), C.byref(l), C.byref(r) if r is not None else None,
                                 T, dt, C.byref(p), C.byref(tr) if tr is not None else None,
                                 C.byref(m) if m is not None else None, _tune(tune), ws.data_ptr(), ws.numel(),
@@ -402,7 +483,13 @@ def rollout_idm(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: 
 def rollout_backward(batch: Batch, init: State, act_seq: Action, log_seq: State, T: int, dt: float, ckpt_every: int,
                      ckpt: State, dloss: torch.Tensor, grad_accel: torch.Tensor, grad_curvature: torch.Tensor,
                      ws: torch.Tensor, stream=None):
-    b, i, a, l, ck = batch.c(), init.c(), act_seq.c(), log_seq.c(), ckpt.c()
+    N = batch.total_objects
+    b, i, a, l = batch.c(), init.c(N, "init"), act_seq.c(T * N, N), log_seq.c((T + 1) * N, "log_seq")
+    ck = ckpt.c(-(-T // max(ckpt_every, 1)) * N, "ckpt")
+    _need(dloss, batch.num_scenarios, torch.float32, "dloss", False)
+    _need(grad_accel, T * N, torch.float32, "grad_accel", False)
+    _need(grad_curvature, T * N, torch.float32, "grad_curvature", False)
+    _need(ws, 0, torch.uint8, "ws", False)
     _check(lib().wm_rollout_backward(C.byref(b), C.byref(i), C.byref(a), C.byref(l), T, dt, ckpt_every,
                                      C.byref(ck), dloss.data_ptr(), grad_accel.data_ptr(), grad_curvature.data_ptr(),
                                      ws.data_ptr(), ws.numel(), _stream(stream)))
@@ -410,8 +497,10 @@ def rollout_backward(batch: Batch, init: State, act_seq: Action, log_seq: State,
 
 def autotune(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: Optional[Roadgraph], T: int, dt: float,
              ws: torch.Tensor, stream=None):
-    b, i, a, l = batch.c(), init.c(), act_seq.c(), log_seq.c()
-    r = rg.c() if rg is not None else None
+    N = batch.total_objects
+    b, i, a, l = batch.c(), init.c(N, "init"), act_seq.c(T * N, N), log_seq.c((T + 1) * N, "log_seq")
+    r = rg.c(batch.total_rg_points) if rg is not None else None
+    _need(ws, 0, torch.uint8, "ws", False)
     best = CTuning(0, 0)
     _check(lib().wm_autotune(C.byref(b), C.byref(i), C.byref(a), C.byref(l), C.byref(r) if r is not None else None,
                              T, dt, ws.data_ptr(), ws.numel(), C.byref(best), _stream(stream)))

@@ -146,3 +146,28 @@ def assert_traj_close(g, o, where=""):
             raise AssertionError("%s field %s: %d beyond 1e-4 of the scene scale, first %s gpu=%s oracle=%s" % (
                 where, f, (~ok).sum(), bad, np.asarray(g[f]).reshape(-1)[bad], np.asarray(o[f]).reshape(-1)[bad]))
     np.testing.assert_array_equal(g["valid"], o["valid"], err_msg=where + " valid")
+
+
+# Gradient tolerance: per scenario the norm error ||g - o|| / ||o|| <= 1e-3;
+# the element-wise maximum |g - o| / max |o| is reported beside it and held to
+# the same 1e-3.
+GRAD_TOL = 1e-3
+
+
+def grad_errors(g, o):
+    """(norm error, element-wise maximum error) of one scenario's gradient:
+    ||g - o||_2 / ||o||_2 and max |g - o| / max |o|."""
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    scale = np.abs(o).max()
+    return float(np.linalg.norm(g - o) / np.linalg.norm(o)), float(np.abs(g - o).max() / scale)
+
+
+def assert_grad_close(g, o, where=""):
+    """Bound both gradient errors of one scenario and print them (the
+    element-wise maximum is reported next to the norm error)."""
+    norm, elem = grad_errors(g, o)
+    print("gradient %s: norm error %.3e, element-wise max %.3e" % (where, norm, elem))
+    assert norm <= GRAD_TOL, (where, "norm", norm)
+    assert elem <= GRAD_TOL, (where, "element-wise", elem)
+    return norm, elem

@@ -188,3 +188,86 @@ def test_idm_rollout_rejects_bad_parameters(bad):
     rc = wm.lib().wm_rollout_idm(C.byref(b), C.byref(_state()), C.byref(_act()), C.byref(_state()), None, 10, 0.1,
                                  None, None, None, None, FAKE, 1 << 30, None)
     assert rc == 1             # WM_ERR_NULL
+
+
+# The boundary's calls as the scope table of this build names them: the
+# step, the inverse, the two metrics, the observation, the rollout and its
+# adjoint, the rollout's workspace query and the two error reporters.
+BOUNDARY_CALLS = ("wm_step", "wm_inverse_action", "wm_overlap", "wm_offroad", "wm_observe", "wm_rollout",
+                  "wm_rollout_backward", "wm_rollout_workspace_bytes", "wm_error_string", "wm_last_error_message")
+
+
+def test_boundary_calls_are_declared_and_exported():
+    names = declared_functions()
+    lib = wm.lib()
+    for name in BOUNDARY_CALLS:
+        assert name in names, name
+        assert hasattr(lib, name), name
+    b = _batch()
+    for T, K in ((0, 0), (80, 10), (7, 3)):
+        assert lib.wm_rollout_workspace_bytes(C.byref(b), T, K) == lib.wm_workspace_bytes(C.byref(b), T, K)
+
+
+def _cpu_batch(counts=(3, 4), points=(10, 12)):
+    import numpy as np
+    obj_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    rg_off = np.concatenate([[0], np.cumsum(points)]).astype(np.int32)
+    return wm.Batch.from_offsets(obj_off, rg_off, "cpu")
+
+
+def _cpu_state(n, dtype=None):
+    import torch
+    st = wm.State.empty((n,), "cpu")
+    if dtype is not None:
+        st.x = st.x.to(dtype)
+    return st
+
+
+def test_binding_rejects_short_or_mistyped_tensors():
+    """Sizes and dtypes are checked in the binding before any pointer reaches
+    the library (a short tensor would otherwise be written past its end)."""
+    import torch
+    b = _cpu_batch()
+    n, P = b.total_objects, b.total_rg_points
+    act = wm.Action(torch.zeros(n), torch.zeros(n), torch.ones(n, dtype=torch.uint8))
+    rg = wm.Roadgraph(torch.zeros(P), torch.zeros(P), torch.zeros(P), torch.zeros(P),
+                      torch.zeros(P, dtype=torch.int8), torch.ones(P, dtype=torch.uint8))
+    good = _cpu_state(n)
+    with pytest.raises(ValueError, match="next.x has 6 elements"):
+        wm.step(b, good, act, good, None, 0.1, _cpu_state(n - 1))
+    with pytest.raises(ValueError, match="dtype"):
+        wm.step(b, _cpu_state(n, torch.float64), act, good, None, 0.1, _cpu_state(n))
+    short_act = wm.Action(torch.zeros(n), torch.zeros(n - 2), act.controlled)
+    with pytest.raises(ValueError, match="curvature"):
+        wm.step(b, good, short_act, good, None, 0.1, _cpu_state(n))
+    with pytest.raises(ValueError, match="metrics.offroad_margin"):
+        wm.step(b, good, act, good, rg, 0.1, _cpu_state(n), wm.Metrics(offroad_margin=torch.zeros(n - 1)))
+    short_rg = wm.Roadgraph(rg.x[:-1], rg.y, rg.dir_x, rg.dir_y, rg.type, rg.valid)
+    with pytest.raises(ValueError, match="rg.x"):
+        wm.offroad(b, good, short_rg, torch.zeros(64, dtype=torch.uint8), margin=torch.zeros(n))
+    with pytest.raises(ValueError, match="nearest"):
+        wm.offroad(b, good, rg, torch.zeros(64, dtype=torch.uint8), nearest=torch.zeros(4 * n - 1, dtype=torch.int32))
+    ego = torch.zeros(2 * 2, dtype=torch.int32)
+    with pytest.raises(ValueError, match="rg_idx"):
+        wm.observe(b, good, rg, ego, 2, 5, torch.zeros(2 * 2 * 5 - 1, dtype=torch.int32))
+    with pytest.raises(ValueError, match="obj_feat"):
+        wm.observe(b, good, rg, ego, 2, 5, torch.zeros(20, dtype=torch.int32),
+                   obj_feat=torch.zeros(2 * 2 * 4 * 8 - 1))
+    T = 3
+    seq_act = wm.Action(torch.zeros(T * n), torch.zeros(T * n), act.controlled)
+    log = _cpu_state((T + 1) * n)
+    ws = torch.zeros(64, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="traj.y"):
+        tr = _cpu_state(T * n)
+        tr.y = tr.y[:-1]
+        wm.rollout(b, good, seq_act, log, None, T, 0.1, ws, traj=tr)
+    with pytest.raises(ValueError, match="log_seq"):
+        wm.rollout(b, good, seq_act, _cpu_state(T * n), None, T, 0.1, ws)
+    with pytest.raises(ValueError, match="loss"):
+        wm.rollout(b, good, seq_act, log, None, T, 0.1, ws, loss=torch.zeros(1))
+    with pytest.raises(ValueError, match="grad_curvature"):
+        wm.rollout_backward(b, good, seq_act, log, T, 0.1, 2, _cpu_state(2 * n), torch.ones(2), torch.zeros(T * n),
+                            torch.zeros(T * n - 1), ws)
+    with pytest.raises(ValueError, match="batch.obj_off"):
+        bad = wm.Batch(b.obj_off.to(torch.int64), b.rg_off, 2, n, P, 4, 12)
+        wm.step(bad, good, act, good, None, 0.1, _cpu_state(n))

@@ -1,7 +1,7 @@
 """The bench's count of the adjoint's evaluated pair terms (the work its
-roofline figure is taken on), on small hand-placed scenes on the CPU: every
-controlled object counts its pair with itself, partners beyond the distance
-bound do not count, partners within it do."""
+roofline figure is taken on), on small hand-placed scenes on the CPU: an
+object is never its own partner, partners beyond the distance bound do not
+count, partners within it do."""
 import math
 import os
 import sys
@@ -30,12 +30,12 @@ def _scene(xs, ys, T, length=4.0, width=2.0):
     return off, init, log, traj
 
 
-def test_far_apart_objects_count_only_themselves():
+def test_far_apart_objects_count_nothing():
     T = 5
     off, init, log, traj = _scene([0.0, 100.0, 200.0], [0.0, 0.0, 0.0], T)
     ctrl = torch.tensor([1, 1, 0], dtype=torch.uint8)
     ops, near, tested = bench.adjoint_executed_ops(off, ctrl, init, log, traj, T)
-    assert near == T * 2                  # each controlled object with itself
+    assert near == 0                      # no partner within the bound, never itself
     assert tested == T * 2 * 2            # partners other than itself
     assert ops == T * (bench.ADJ_OPS_PER_TEST * 2 * 3 + bench.ADJ_OPS_PER_OBJECT * 2) + bench.ADJ_OPS_PER_PAIR * near
 
@@ -48,7 +48,7 @@ def test_bound_edge():
     off, init, log, traj = _scene([0.0, edge - 0.05, -(edge + 0.05)], [0.0, 0.0, 0.0], T)
     ctrl = torch.tensor([1, 0, 0], dtype=torch.uint8)
     _, near, _ = bench.adjoint_executed_ops(off, ctrl, init, log, traj, T)
-    assert near == T * 2                  # itself and the object just inside
+    assert near == T                      # only the object just inside
 
 
 def test_uncontrolled_objects_come_from_the_log():
@@ -59,4 +59,4 @@ def test_uncontrolled_objects_come_from_the_log():
     traj.x[1:, 0] = 495.0
     ctrl = torch.tensor([1, 0], dtype=torch.uint8)
     _, near, _ = bench.adjoint_executed_ops(off, ctrl, init, log, traj, T)
-    assert near == T + (T - 1)
+    assert near == T - 1

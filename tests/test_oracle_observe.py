@@ -96,3 +96,40 @@ def test_frame_transform_properties():
         np.testing.assert_allclose(np.hypot(rf[0, e, :, 2], rf[0, e, :, 3]), 1.0, atol=1e-12)
     # invalid ego: everything padded
     assert (idx[0, 2] == -1).all() and (rf[0, 2] == 0).all() and (of[0, 2] == 0).all()
+
+
+def test_binary32_key_topk_equals_fp64_distance_topk_outside_the_band():
+    """The k nearest road points by the binary32 key (the kernel's precision)
+    are the k nearest by the exact FP64 distance, except points whose
+    distance lies within 1e-4 m of the k-th distance d_k (counted, a few per
+    ego at most); and the binary32 order is the FP64 order except inside
+    runs of distances closer than 1e-4 m."""
+    rng = np.random.default_rng(33)
+    band = 1e-4
+    in_band = 0
+    for trial in range(6):
+        P = int(rng.integers(1500, 6000))
+        k = int(rng.choice([50, 333, 1000]))
+        # float32 inputs at the scene scale of the workloads (100 m box)
+        pts = rng.uniform(-100, 100, (P, 2)).astype(np.float32).astype(np.float64)
+        valid = (rng.random(P) > 0.05).astype(np.uint8)
+        ego_xy = rng.uniform(-80, 80, (4, 2)).astype(np.float32).astype(np.float64)
+        objs = _objs(ego_xy[:, 0], ego_xy[:, 1], rng.uniform(-3, 3, 4), np.zeros(4), np.zeros(4))
+        idx, _, _ = oracle.observe(np.array([0, 4], np.int32), np.array([0, P], np.int32), objs, _rg(pts, valid),
+                                   np.arange(4, dtype=np.int32)[None], k, 4)
+        cand = np.flatnonzero(valid)
+        for e in range(4):
+            d = np.hypot(pts[:, 0] - ego_xy[e, 0], pts[:, 1] - ego_xy[e, 1])
+            order64 = cand[np.lexsort((cand, d[cand]))]
+            kk = min(k, cand.size)
+            dk = d[order64[kk - 1]]
+            got = idx[0, e, :kk]
+            assert (got >= 0).all() and (idx[0, e, kk:] == -1).all()
+            sym = np.setxor1d(got, order64[:kk])
+            near = np.abs(d[sym] - dk) < band
+            assert near.all(), (trial, e, sym[~near], d[sym[~near]], dk)
+            in_band += sym.size
+            # order: FP64 distance never decreases by more than the band
+            dd = d[got]
+            assert (np.diff(dd) > -band).all()
+    assert in_band <= 6 * 4 * 4, in_band
