@@ -181,6 +181,26 @@ int wm_step_prepared(const wm_batch *batch, const wm_state *cur, const wm_action
                      const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *metrics, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* Bytes of the device-resident workspace of wm_step_noalloc: one copy per
+ * device the library runs on, held until the process ends. */
+#define WM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* wm_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and outputs as wm_step, with the workspace taken from a device
+ * array of WM_NOALLOC_SCRATCH_BYTES that the library holds instead of a ws
+ * argument.  Calls no hipMalloc, hipFree or allocating library routine; the
+ * first call on a device looks up that device's array address (a host-side
+ * query, not a stream operation).  Fails with WM_ERR_UNSUPPORTED, before any
+ * launch, when off-road metrics are requested and wm_workspace_bytes(batch,
+ * 0, 0) exceeds WM_NOALLOC_SCRATCH_BYTES (64 MiB holds about 2.7 million road
+ * points per batch).  Every call on one device shares that device's array and
+ * it keeps the last call's contents (nothing in it needs to start at zero):
+ * calls that overlap in time on one device (several streams or threads) race
+ * on it, so the caller must order them, e.g. on one stream. */
+int wm_step_noalloc(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+                    const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *metrics, void *stream);
+
 /* Expert action by inverse kinematics (App. A.1, inverse kinematics
  * equation; Sec. 5.2 Expert): a = (|v'| - |v|)/dt,
  * kappa = wrap(atan2(vy', vx') - yaw) / (|v| dt + a dt^2/2), kappa = 0 when

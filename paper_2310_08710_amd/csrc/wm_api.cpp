@@ -269,12 +269,17 @@ int wm_profile_collect(int which, float *total_ms, int32_t *launches)
     return rc == WM_OK ? ok() : rc;
 }
 
-// `prepared`: the workspace already holds this road graph's compacted edges
-// (wm_roadgraph_prepare), so the compaction is skipped.
+enum class StepWs { Given, Prepared, Scratch };
+
+// `Prepared`: the workspace already holds this road graph's compacted edges
+// (wm_roadgraph_prepare), so the compaction is skipped.  `Scratch`: the
+// workspace is the device's WM_NOALLOC_SCRATCH_BYTES array (ws is ignored).
 static int step_impl(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
                      const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
-                     void *stream, bool prepared)
+                     void *stream, StepWs wsk)
 {
+    const bool prepared = wsk == StepWs::Prepared;
+    const char *name = wsk == StepWs::Given ? "wm_step" : prepared ? "wm_step_prepared" : "wm_step_noalloc";
     CHECK(check_batch(batch));
     CHECK(check_state(cur, "cur"));
     CHECK(check_state(log_next, "log_next"));
@@ -290,6 +295,19 @@ static int step_impl(const wm_batch *batch, const wm_state *cur, const wm_action
     if (m && m->reward && (!m->collision || (rg && !m->offroad)))
         return fail(WM_ERR_NULL, "reward needs the collision (and, with a road graph, offroad) outputs");
     const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
+    if (want_off && wsk == StepWs::Scratch && L.total > WM_NOALLOC_SCRATCH_BYTES)
+        return fail(WM_ERR_UNSUPPORTED,
+                    "wm_step_noalloc: off-road metrics of this batch (%d scenarios, %d road points) need %zu bytes "
+                    "of workspace, more than the %zu of the device scratch; use wm_step with a workspace",
+                    batch->num_scenarios, batch->total_rg_points, L.total, (size_t)WM_NOALLOC_SCRATCH_BYTES);
+    if (want_off && wsk == StepWs::Scratch) {
+        unsigned char *p = nullptr;
+        const hipError_t e = wm::noalloc_scratch(&p);
+        if (e != hipSuccess)
+            return fail(WM_ERR_DEVICE, "wm_step_noalloc: device scratch address: %s", hipGetErrorString(e));
+        ws = p;
+        ws_bytes = WM_NOALLOC_SCRATCH_BYTES;
+    }
     if (want_off)
         CHECK(check_ws(ws, ws_bytes, L.total));
     hipStream_t st = (hipStream_t)stream;
@@ -316,21 +334,27 @@ static int step_impl(const wm_batch *batch, const wm_state *cur, const wm_action
     }
     if (m && m->reward)
         wm::launch_reward(*batch, m->collision, rg ? m->offroad : nullptr, m->reward, st);
-    return device_status(prepared ? "wm_step_prepared" : "wm_step");
+    return device_status(name);
 }
 
 int wm_step(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
             const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
             void *stream)
 {
-    return step_impl(batch, cur, act, log_next, rg, dt, next, m, ws, ws_bytes, stream, false);
+    return step_impl(batch, cur, act, log_next, rg, dt, next, m, ws, ws_bytes, stream, StepWs::Given);
 }
 
 int wm_step_prepared(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
                      const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *ws, size_t ws_bytes,
                      void *stream)
 {
-    return step_impl(batch, cur, act, log_next, rg, dt, next, m, ws, ws_bytes, stream, true);
+    return step_impl(batch, cur, act, log_next, rg, dt, next, m, ws, ws_bytes, stream, StepWs::Prepared);
+}
+
+int wm_step_noalloc(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+                    const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *m, void *stream)
+{
+    return step_impl(batch, cur, act, log_next, rg, dt, next, m, nullptr, 0, stream, StepWs::Scratch);
 }
 
 int wm_roadgraph_prepare(const wm_batch *batch, const wm_roadgraph *rg, void *ws, size_t ws_bytes, void *stream)

@@ -179,5 +179,8 @@ void launch_loss_reduce(int S, const int32_t *uoff, const float *lossp, float *l
 void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream_t st);
 int backward_block_steps(int maxN, int K);
 void launch_backward(const BackwardArgs &a, hipStream_t st);
+// Device address of the current device's WM_NOALLOC_SCRATCH_BYTES scratch
+// array (looked up on the first call per device).
+hipError_t noalloc_scratch(unsigned char **out);
 
 } // namespace wm

@@ -1228,4 +1228,37 @@ void launch_loss_reduce(int S, const int32_t *uoff, const float *lossp, float *l
     hipLaunchKernelGGL(k_loss_reduce, dim3((S + 255) / 256), dim3(256), 0, st, S, uoff, lossp, loss);
 }
 
+// ---------------------------------------------------------------------------
+// Device-resident workspace of wm_step_noalloc, for callers that cannot
+// allocate: WM_NOALLOC_SCRATCH_BYTES per device, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[WM_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(unsigned char **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static unsigned char *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        ptr[dev] = (unsigned char *)p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
 } // namespace wm

@@ -97,6 +97,8 @@ def lib() -> C.CDLL:
                               C.POINTER(CRoadgraph), C.c_float, C.POINTER(CState), C.POINTER(CMetrics), _P,
                               C.c_size_t, _P]
         L.wm_step_prepared.argtypes = L.wm_step.argtypes
+        L.wm_step_noalloc.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
+                                      C.POINTER(CRoadgraph), C.c_float, C.POINTER(CState), C.POINTER(CMetrics), _P]
         L.wm_roadgraph_prepare.argtypes = [C.POINTER(CBatch), C.POINTER(CRoadgraph), _P, C.c_size_t, _P]
         L.wm_inverse_action.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CState), C.c_float, _P, _P,
                                         _P, _P]
@@ -328,6 +330,17 @@ def _step(fn, batch, cur, act, log_next, rg, dt, nxt, metrics, ws, stream):
 def step(batch: Batch, cur: State, act: Action, log_next: State, rg: Optional[Roadgraph], dt: float, nxt: State,
          metrics: Optional[Metrics] = None, ws: Optional[torch.Tensor] = None, stream=None):
     _step(lib().wm_step, batch, cur, act, log_next, rg, dt, nxt, metrics, ws, stream)
+
+
+def step_noalloc(batch: Batch, cur: State, act: Action, log_next: State, rg: Optional[Roadgraph], dt: float,
+                 nxt: State, metrics: Optional[Metrics] = None, stream=None):
+    """step() with the library's device-resident workspace (no ws argument)."""
+    N = batch.total_objects
+    b, c, a, l, n = batch.c(), cur.c(N, "cur"), act.c(N, N), log_next.c(N, "log_next"), nxt.c(N, "next")
+    r = rg.c(batch.total_rg_points) if rg is not None else None
+    m = metrics.c(N) if metrics is not None else None
+    _check(lib().wm_step_noalloc(C.byref(b), C.byref(c), C.byref(a), C.byref(l), C.byref(r) if r is not None else None,
+                                 dt, C.byref(n), C.byref(m) if m is not None else None, _stream(stream)))
 
 
 def roadgraph_prepare(batch: Batch, rg: Roadgraph, ws: torch.Tensor, stream=None):

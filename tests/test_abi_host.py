@@ -97,6 +97,32 @@ def test_step_validation():
     assert step(rg=wm.CRoadgraph(FAKE, FAKE, None, FAKE, FAKE, FAKE), m=m) == wm.WM_ERR_NULL
 
 
+def test_step_noalloc_validation():
+    """The device-scratch step validates like wm_step and rejects a batch
+    whose off-road workspace exceeds its WM_NOALLOC_SCRATCH_BYTES (64 MiB)
+    before any device call."""
+    lib = wm.lib()
+    m = wm.CMetrics(None, FAKE, None, None, None)
+
+    def call(batch=None, cur=None, rg=None, m=None, dt=0.1):
+        b = batch if batch is not None else _batch()
+        c = cur if cur is not None else _state()
+        return lib.wm_step_noalloc(C.byref(b), C.byref(c), C.byref(_act()), C.byref(_state()),
+                                   C.byref(rg) if rg is not None else None, dt,
+                                   C.byref(wm.CState(*([FAKE + 64] * 8))), C.byref(m) if m is not None else None,
+                                   None)
+
+    assert lib.wm_step_noalloc(None, None, None, None, None, 0.1, None, None, None) == wm.WM_ERR_NULL
+    assert call(batch=_batch(S=0)) == wm.WM_ERR_RANGE
+    assert call(cur=_state(null_field=2)) == wm.WM_ERR_NULL
+    assert call(dt=0.0) == wm.WM_ERR_RANGE
+    # 3 million road points: 24 bytes of workspace per point slot > 64 MiB
+    big = wm.CBatch(4, 400, 3000000, 100, 750000, FAKE, FAKE)
+    assert lib.wm_workspace_bytes(C.byref(big), 0, 0) > 64 << 20
+    assert call(batch=big, rg=_rg(), m=m) == wm.WM_ERR_UNSUPPORTED
+    assert "wm_step_noalloc" in _msg() and "scratch" in _msg()
+
+
 def test_offroad_and_tuning_validation():
     L = wm.lib()
     b, s, r = _batch(), _state(), _rg()
