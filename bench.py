@@ -8,13 +8,19 @@ scenes shaped like the paper's runtime benchmark, Sec. 5.1 / App. A.3).  One
 timed step is one expert rollout (RolloutExpert in the paper's runtime
 table): expert actions from inverse kinematics on the logs, then the fused
 persistent rollout kernel with every metric (collision, off-road,
-displacement) at every step.  value = agent-steps/s = objects x 80 x K / time.
+displacement) at every step.  The step is captured once as a HIP graph and
+the K timed steps are K replays: value = agent-steps/s = valid objects x 80 x
+K / wall time; the per-replay median and minimum come from HIP events
+between the replays.
 
 Also reported on the same line: the dominant kernel against the FP32 roofline
-(HIP events around the persistent kernel), the FP64 CPU oracle on a bounded
-sample of the same workload, the plain per-step form (separate launches per
-operation, captured in a HIP graph), the differentiable rollout (forward +
-adjoint) and the observation (8 egos per scenario, k = 1000).
+(HIP events around the persistent kernel over K more steps), the FP64 CPU
+oracle on bounded samples of the workloads, the plain per-step form
+(separate launches per operation, captured in a HIP graph), the
+differentiable rollout (forward + adjoint) of the configurations with
+8 and with all objects controlled, the observation (8 egos per scenario,
+k = 1000), the ragged batches of 1,024 and 4,096 scenarios, the closed loop
+of step + observation, IDM agents and the per-step latency at batch 1 and 16.
 Progress goes to stderr; stdout carries exactly one JSON line.
 """
 from __future__ import annotations
@@ -101,15 +107,60 @@ def adjoint_executed_ops(obj_off, controlled, init, log_seq, traj, T):
     return float(ops), float(near), float(T * nc * (N - 1))
 
 
-def adjoint_ops(scene, controlled):
-    """Algorithmic ops of one adjoint launch over the scene's T steps; every
-    object is valid in the synthetic scenes."""
-    ctrl = np.asarray(controlled).astype(bool)
-    off = np.asarray(scene.obj_off)
-    nc = np.add.reduceat(ctrl.astype(np.int64), off[:-1]) if len(off) > 1 else np.zeros(0)
-    N = np.diff(off).astype(np.int64)
-    pairs = float((nc * np.maximum(N - 1, 0)).sum())
-    return scene.steps * (ADJ_OPS_PER_PAIR * pairs + ADJ_OPS_PER_OBJECT * float(nc.sum())), scene.steps * pairs
+# The method's work of the adjoint, as counted for its roofline: per scenario
+# and step, every unordered pair of valid objects with a controlled member
+# (nc (N - 1) - nc (nc - 1) / 2 pairs; 988 at N = 128 with 8 controlled) costs
+# about 40 FP32 ops for the separating-axis margin and its soft-overlap term,
+# three times over (the recomputed forward, the term, its reverse).  The
+# executed count above sits beside it: the kernel skips pairs whose term is
+# exactly zero in FP32.
+ADJ_ALG_OPS_PER_PAIR = 120
+
+
+def adjoint_algorithmic_ops(obj_off, controlled, valid, T):
+    """(ops, pairs) of one adjoint launch over T steps by the count above;
+    host arrays, `valid` of the initial state."""
+    off = np.asarray(obj_off).astype(np.int64)
+    ctrl = (np.asarray(controlled) != 0) & (np.asarray(valid) != 0)
+    vld = np.asarray(valid) != 0
+    cc = np.concatenate([[0], np.cumsum(ctrl)])
+    cv = np.concatenate([[0], np.cumsum(vld)])
+    nc = cc[off[1:]] - cc[off[:-1]]
+    nv = cv[off[1:]] - cv[off[:-1]]
+    pairs = float(np.sum(nc * np.maximum(nv - 1, 0) - nc * (nc - 1) // 2))
+    return ADJ_ALG_OPS_PER_PAIR * pairs * T, pairs * T
+
+
+# Algorithmic work of the default observation per ego and state row: each of
+# the scenario's P_s road points costs 5 FP32 ops for its key dx^2 + dy^2 from
+# the ego centre (two differences, a product and an FMA) and 4 for one
+# selection pass (compare with the bound, count, place).  Bytes written: k
+# road entries of 20 B (index and four features) and max_objects object
+# entries of 32 B; the bound is HBM (the writes), with the VALU fraction
+# beside it.
+OBS_OPS_PER_POINT = 9
+
+
+def observe_roofline(out_bytes, ops, kernel_ms):
+    sec = kernel_ms * 1e-3
+    return {"bound": "hbm", "achieved": out_bytes / sec / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": out_bytes / sec / PEAK_HBM, "traffic": None, "kernel": "k_observe", "kernel_ms": kernel_ms,
+            "bytes_per_launch": out_bytes,
+            "valu": {"achieved": ops / sec / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": ops / sec / PEAK_FP32, "ops_per_launch": ops}}
+
+
+def adjoint_roofline(alg_ops, alg_pairs, xops, xnear, kernel_ms):
+    """The adjoint kernel against the FP32 peak by the method's count, with
+    the executed count beside it."""
+    sec = kernel_ms * 1e-3
+    r = {"bound": "alu", "achieved": alg_ops / sec / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+         "frac": alg_ops / sec / PEAK_FP32, "kernel": "k_rollout_backward", "kernel_ms": kernel_ms,
+         "ops_per_launch": alg_ops, "pair_steps_with_a_controlled_member": alg_pairs}
+    if xops is not None:
+        r["executed"] = {"ops_per_launch": xops, "pair_terms_evaluated": xnear, "achieved": xops / sec / 1e12,
+                         "frac": xops / sec / PEAK_FP32}
+    return r
 
 
 # The sources k_rollout is compiled from: its counters stay valid while these
@@ -139,31 +190,111 @@ def recorded_traffic(tune):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(scene, sample, threads):
-    """The FP64 oracle (as it stands) on the first `sample` scenarios of the
-    workload, one scenario per thread; agent-steps/s."""
-    import oracle
+def cpu_info():
+    """nproc, the cores this process may run on and the CPU model string."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "model": model}
+
+
+def _f64(d):
+    return {k: (v.astype(np.float64) if v.dtype == np.float32 else v) for k, v in d.items()}
+
+
+def _scenario(scene, lw, s):
+    """Host inputs of scenario s alone (local offsets)."""
+    o0, o1 = int(scene.obj_off[s]), int(scene.obj_off[s + 1])
+    p0, p1 = int(scene.rg_off[s]), int(scene.rg_off[s + 1])
+    sub = {k: v[:, o0:o1] for k, v in lw.items()}
+    return (np.array([0, o1 - o0], np.int32), np.array([0, p1 - p0], np.int32), sub,
+            _f64({k: v[p0:p1] for k, v in scene.rg.items()}), scene.accel[:, o0:o1], scene.curvature[:, o0:o1],
+            scene.controlled[o0:o1])
+
+
+def _pool_time(fn, items, threads):
+    """Wall time of fn over items on `threads` threads (the oracle's C calls
+    release the interpreter lock, so the threads run in parallel)."""
     from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    if threads == 1:
+        res = [fn(i) for i in items]
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            res = list(ex.map(fn, items))
+    return res, time.perf_counter() - t0
+
+
+def cpu_forward(scene, scen_ids, threads):
+    """The FP64 oracle's rollout with every metric on the given scenarios, one
+    scenario per task: (agent-steps/s, wall seconds)."""
+    import oracle
     lw = scene.log_window()
     T = scene.steps
 
     def one(s):
-        o0, o1 = int(scene.obj_off[s]), int(scene.obj_off[s + 1])
-        p0, p1 = int(scene.rg_off[s]), int(scene.rg_off[s + 1])
-        sub = {k: v[:, o0:o1] for k, v in lw.items()}
-        f64 = lambda d: {k: (v.astype(np.float64) if v.dtype == np.float32 else v) for k, v in d.items()}  # noqa
-        rg = f64({k: v[p0:p1] for k, v in scene.rg.items()})
-        oracle.rollout(np.array([0, o1 - o0], np.int32), np.array([0, p1 - p0], np.int32),
-                       f64({k: v[0] for k, v in sub.items()}), scene.accel[:, o0:o1], scene.curvature[:, o0:o1],
-                       scene.controlled[o0:o1], f64(sub), rg, T, scene.dt, metrics=True, want_loss=False)
-        return o1 - o0
+        oo, ro, sub, rg, a, k, c = _scenario(scene, lw, s)
+        oracle.rollout(oo, ro, _f64({q: v[0] for q, v in sub.items()}), a, k, c, _f64(sub), rg, T, scene.dt,
+                       metrics=True, want_loss=False)
+        return int(sub["valid"][0].sum())
 
     oracle.lib()
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        objs = sum(ex.map(one, range(sample)))
-    dt = time.perf_counter() - t0
-    return objs * T / dt, dt
+    objs, wall = _pool_time(one, scen_ids, threads)
+    return sum(objs) * T / wall, wall
+
+
+def cpu_fwd_bwd(scene, scen_ids, threads):
+    """The FP64 oracle's loss and hand-written reverse-mode gradient (its
+    forward runs inside, with a full tape) on the given scenarios:
+    (rollout scenario-steps/s, wall seconds)."""
+    import oracle
+    lw = scene.log_window()
+    T = scene.steps
+
+    def one(s):
+        oo, _, sub, _, a, k, c = _scenario(scene, lw, s)
+        oracle.rollout_grad(oo, _f64({q: v[0] for q, v in sub.items()}), a, k, c, _f64(sub), T, scene.dt)
+        return 1
+
+    oracle.lib()
+    n, wall = _pool_time(one, scen_ids, threads)
+    return sum(n) * T / wall, wall
+
+
+def cpu_baselines(scene1, threads):
+    """The oracle as it stands on the host cores: the config-1 forward on all
+    `threads` and on one thread, and fwd+bwd samples of the differentiable
+    and the 4,096-scenario workloads."""
+    from paper_2310_08710_amd import synth
+    info = cpu_info()
+    sample = 2 * threads
+    rate, wall = cpu_forward(scene1, range(sample), threads)
+    rate1, wall1 = cpu_forward(scene1, range(1), 1)
+    out = {"value": rate, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
+           "sample": "%d of the 256 scenarios of the bench workload, all 80 steps with every metric, FP64 C oracle, "
+                     "one scenario per thread (%.1f s wall)" % (sample, wall),
+           "nproc": info["nproc"], "usable_cores": info["usable_cores"], "cpu_model": info["model"],
+           "single_thread": {"value": rate1, "unit": "agent-steps/s", "sample": "scenario 0 (%.1f s)" % wall1}}
+    log("cpu oracle: %.3e agent-steps/s on %d threads (%.1f s); one thread %.3e" % (rate, threads, wall, rate1))
+    for cfg, key, n_s in ((3, "fwd_bwd_config3", 512), (4, "fwd_bwd_config4", 1024)):
+        sc = synth.make_scene(cfg, scenarios=n_s)
+        r, w = cpu_fwd_bwd(sc, range(n_s), threads)
+        out[key] = {"value": r, "unit": "rollout scenario-steps/s", "cores": threads,
+                    "sample": "%d scenarios of the %s workload, loss-only forward + reverse-mode gradient "
+                              "(full tape), FP64, one scenario per task (%.1f s wall)" % (
+                                  n_s, "512 x 128" if cfg == 3 else "4096-scenario", w)}
+        log("cpu oracle fwd+bwd config %d: %.3e scenario-steps/s (%.1f s)" % (cfg, r, w))
+    return out
 
 
 def main():
@@ -175,7 +306,6 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune", type=str, default=None, help="unit_objects,edge_splits (skips the autotuner)")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="scenarios of the oracle sample")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint of config 1 (every object controlled), for profiling it")
     ap.add_argument("--observe-only", action="store_true",
@@ -246,21 +376,41 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    wm.profile_enable(True)
-    wm.profile_collect(wm.PROF_ROLLOUT)
-    # HIP events between the steps on the stream the steps run on give the
-    # per-step distribution; the wall clock over all K steps gives `value`
+    # the step as one HIP graph (captured on a side stream, replayed on the
+    # current one)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    # timed region: K replays; HIP events between them give the per-step
+    # median and minimum, the wall clock over all K gives `value`
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev[0].record(stream)
     for i in range(args.steps):
-        step()
+        graph.replay()
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
+    del graph
+    # kernel timing: K more steps launched directly, with HIP events around
+    # k_rollout on the stream it runs on (events inside a graph are not timed)
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_ROLLOUT)
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    eager_wall = time.perf_counter() - t1
     kms, launches = wm.profile_collect(wm.PROF_ROLLOUT)
     wm.profile_enable(False)
     valid_objs = int(scene.log["valid"][synth.T0].sum())
@@ -269,8 +419,9 @@ def main():
     kernel_ms = kms / max(launches, 1)
     ops, pairs = rollout_ops(scene, T)
     achieved = ops / (kernel_ms * 1e-3)
-    log("fused rollout: %.3f ms/step, kernel %.3f ms, %.3e agent-steps/s, %.1f TFLOP/s algorithmic" % (
-        ms_per_step, kernel_ms, value, achieved / 1e12))
+    log("fused rollout (graph replays): %.3f ms/step (median %.3f, min %.3f), kernel %.3f ms, %.3e agent-steps/s, "
+        "%.1f TFLOP/s algorithmic" % (ms_per_step, step_ms[len(step_ms) // 2], step_ms[0], kernel_ms, value,
+                                      achieved / 1e12))
     assert torch.isfinite(met.offroad_margin).all() and torch.isfinite(traj.x).all()
 
     out = {
@@ -283,6 +434,8 @@ def main():
         "ms_per_step": ms_per_step,
         "step_ms_median": step_ms[len(step_ms) // 2],
         "step_ms_min": step_ms[0],
+        "timing": "K replays of the step captured as one HIP graph; the kernel time comes from K more steps "
+                  "launched directly (%.3f ms per step)" % (1e3 * eager_wall / args.steps),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -298,20 +451,39 @@ def main():
     }
 
     if not args.no_extras:
-        extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune)
+        extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune, traj, met)
 
     if not args.no_cpu:
-        try:
-            threads = len(os.sched_getaffinity(0))
-        except AttributeError:
-            threads = os.cpu_count() or 1
-        threads = max(1, min(threads, 16, args.cpu_sample))
-        rate, secs = cpu_baseline(scene, args.cpu_sample, threads)
-        out["cpu_baseline"] = {"value": rate, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
-                               "sample": "%d of the 256 scenarios, all 80 steps with every metric, FP64 C oracle, "
-                                         "one scenario per thread (%.1f s wall)" % (args.cpu_sample, secs)}
-        log("cpu oracle: %.3e agent-steps/s on %d threads (%.1f s)" % (rate, threads, secs))
+        threads = max(1, min(cpu_info()["usable_cores"], 16))
+        out["cpu_baseline"] = cpu_baselines(scene, threads)
     print(json.dumps(out), flush=True)
+
+
+def observe_once(scene, ds, dev, st, reps=3, E=8, K=1000):
+    """Time the default observation of one state row for every scenario's E
+    egos (k = K): wall ms per call and the k_observe roofline entry."""
+    import torch
+    from paper_2310_08710_amd import wm
+    S = scene.num_scenarios
+    P = float(np.sum(np.diff(scene.rg_off)))
+    idx = torch.empty(S * E * K, dtype=torch.int32, device=dev)
+    rf = torch.empty(S * E * K * 4, device=dev)
+    of = torch.empty(S * E * ds.batch.max_objects * 8, device=dev)
+    wm.observe(ds.batch, st, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_OBSERVE)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        wm.observe(ds.batch, st, ds.rg, ds.ego, E, K, idx, rf, of)
+    torch.cuda.synchronize()
+    oms = 1e3 * (time.perf_counter() - t0) / reps
+    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
+    wm.profile_enable(False)
+    out_bytes = S * E * (K * 20.0 + ds.batch.max_objects * 32.0)
+    ops = OBS_OPS_PER_POINT * P * E
+    okm = kms / max(kl, 1)
+    return oms, observe_roofline(out_bytes, ops, okm), (idx, rf, of)
 
 
 def observation(out, scene, ds, dev, rows_state, reps=3):
@@ -325,29 +497,14 @@ def observation(out, scene, ds, dev, rows_state, reps=3):
     S, T = scene.num_scenarios, scene.steps
     E, K = 8, 1000
     point_bytes = 9.0 * float(np.sum(np.diff(scene.rg_off))) * E
-    idx = torch.empty(S * E * K, dtype=torch.int32, device=dev)
-    rf = torch.empty(S * E * K * 4, device=dev)
-    of = torch.empty(S * E * ds.batch.max_objects * 8, device=dev)
-    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
-    torch.cuda.synchronize()
-    wm.profile_enable(True)
-    wm.profile_collect(wm.PROF_OBSERVE)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, K, idx, rf, of)
-    torch.cuda.synchronize()
-    oms = 1e3 * (time.perf_counter() - t0) / reps
-    kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
-    wm.profile_enable(False)
-    out_bytes = S * E * (K * 20 + ds.batch.max_objects * 32)
-    okm = kms / max(kl, 1)
+    oms, roof, bufs = observe_once(scene, ds, dev, ds.init, reps, E, K)
+    del bufs
+    okm = roof["kernel_ms"]
     out["observe"] = {"egos_per_s": S * E / (oms * 1e-3), "ms": oms, "kernel_ms": okm, "k": K, "egos": S * E,
-                      "output_GBps": out_bytes / (okm * 1e-3) / 1e9,
-                      "point_reads_TBps": point_bytes / (okm * 1e-3) / 1e12}
-    log("observe: %.3f ms for %d egos (kernel %.3f ms)" % (oms, S * E, okm))
+                      "roofline": roof, "point_reads_TBps": point_bytes / (okm * 1e-3) / 1e12}
+    log("observe: %.3f ms for %d egos (kernel %.3f ms, %.1f%% of HBM)" % (oms, S * E, okm, 100 * roof["frac"]))
 
     # every row of a trajectory in one launch
-    del idx, rf, of
     idx = torch.empty((T, S * E * K), dtype=torch.int32, device=dev)
     rf = torch.empty((T, S * E * K * 4), device=dev)
     of = torch.empty((T, S * E * ds.batch.max_objects * 8), device=dev)
@@ -362,16 +519,18 @@ def observation(out, scene, ds, dev, rows_state, reps=3):
     kms, kl = wm.profile_collect(wm.PROF_OBSERVE)
     wm.profile_enable(False)
     skm = kms / max(kl, 1)
+    out_bytes = T * S * E * (K * 20.0 + ds.batch.max_objects * 32.0)
+    ops = T * OBS_OPS_PER_POINT * float(np.sum(np.diff(scene.rg_off))) * E
+    sroof = observe_roofline(out_bytes, ops, skm)
     out["observe_seq"] = {"ms": sms, "kernel_ms": skm, "rows": T, "egos_per_row": S * E, "k": K,
-                          "ego_steps_per_s": T * S * E / (sms * 1e-3),
-                          "output_GBps": T * out_bytes / (skm * 1e-3) / 1e9,
+                          "ego_steps_per_s": T * S * E / (sms * 1e-3), "roofline": sroof,
                           "point_reads_TBps": T * point_bytes / (skm * 1e-3) / 1e12}
-    log("observe_seq: %.3f ms for %d steps x %d egos" % (sms, T, S * E))
+    log("observe_seq: %.3f ms for %d steps x %d egos (%.1f%% of HBM)" % (sms, T, S * E, 100 * sroof["frac"]))
 
 
-def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
+def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune, fused_traj, fused_met):
     import torch
-    from paper_2310_08710_amd import wm
+    from paper_2310_08710_amd import synth, wm
     S, n, T = scene.num_scenarios, scene.total_objects, scene.steps
     reps = 3
 
@@ -392,57 +551,16 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
             wm.step_prepared(ds.batch, c, act, ds.log_seq.row(t), ds.rg, scene.dt, traj.row(t - 1), m, ws0)
             c = traj.row(t - 1)
 
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        plain()
-    torch.cuda.current_stream().wait_stream(side)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        plain()
-    g.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g.replay()
-    torch.cuda.synchronize()
-    pms = 1e3 * (time.perf_counter() - t0) / reps
+    pms = _time_graph(plain, reps)
     fused_ms = out["ms_per_step"]
+    same = all(torch.equal(getattr(fused_met, f), getattr(met, f)) for f in fields) and \
+        torch.equal(fused_traj.x, traj.x)
     out["plain"] = {"value": n * T / (pms * 1e-3), "unit": "agent-steps/s", "ms_per_rollout": pms,
                     "form": "road-edge compaction once, then per-step launches (dynamics, overlap, off-road) "
                             "in one HIP graph",
-                    "fused_speedup": pms / fused_ms}
-    log("plain graph: %.3f ms/rollout (fused speedup %.2fx)" % (pms, pms / fused_ms))
-    del g
-
-    # fused rollout captured as a graph as well (whole rollout = 1 replay)
-    traj2 = wm.State.empty((T, n), dev)
-    met2 = wm.Metrics.empty((T, n), dev)
-    ws1 = ds.batch.workspace(T, 10)
-
-    def fused():
-        wm.inverse_action(inv_batch, cur, nxt, scene.dt, ea, ek)
-        wm.rollout(ds.batch, ds.init, expert, ds.log_seq, ds.rg, T, scene.dt, ws1, traj=traj2, metrics=met2,
-                   tune=tune)
-
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        fused()
-    torch.cuda.current_stream().wait_stream(side)
-    g2 = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g2):
-        fused()
-    g2.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g2.replay()
-    torch.cuda.synchronize()
-    gms = 1e3 * (time.perf_counter() - t0) / reps
-    out["fused_graph"] = {"ms_per_rollout": gms, "value": n * T / (gms * 1e-3), "unit": "agent-steps/s"}
-    ok = all(torch.equal(getattr(met2, f), getattr(met, f)) for f in fields)
-    out["fused_graph"]["equals_plain"] = bool(ok)
-    del g2
+                    "fused_speedup": pms / fused_ms, "identical_outputs": bool(same)}
+    log("plain graph: %.3f ms/rollout (fused speedup %.2fx, identical %s)" % (pms, pms / fused_ms, same))
+    del traj, met
 
     # differentiable rollout: forward (every metric + loss + checkpoints) + adjoint
     a = ea.clone().requires_grad_(True)
@@ -468,25 +586,153 @@ def extras(out, scene, ds, dev, inv_batch, cur, nxt, ea, ek, expert, tune):
     bms, bl = wm.profile_collect(wm.PROF_BACKWARD)
     wm.profile_enable(False)
     bkm = bms / max(bl, 1)
-    aops, apairs = adjoint_ops(scene, ds.act_seq.controlled.cpu().numpy())
-    # the trajectory of these actions (traj2: the expert rollout, every object controlled)
-    xops, xnear, _ = adjoint_executed_ops(ds.batch.obj_off, ds.act_seq.controlled, ds.init, ds.log_seq, traj2, T)
+    # the trajectory of these actions: the expert rollout, every object controlled
+    xops, xnear, _ = adjoint_executed_ops(ds.batch.obj_off, ds.act_seq.controlled, ds.init, ds.log_seq, fused_traj,
+                                          T)
+    alg, alg_pairs = adjoint_algorithmic_ops(scene.obj_off, scene.controlled, scene.log["valid"][synth.T0], T)
     out["fwd_bwd"] = {"value": S * T / (fbms * 1e-3), "unit": "rollout scenario-steps/s",
                       "agent_steps_per_s": n * T / (fbms * 1e-3), "ms_per_rollout": fbms,
-                      "backward_kernel_ms": bkm, "controlled": "all objects",
-                      "checkpoint_every": 10,
-                      "backward_roofline": {"bound": "alu", "achieved": xops / (bkm * 1e-3) / 1e12,
-                                            "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                                            "frac": xops / (bkm * 1e-3) / PEAK_FP32, "ops_per_launch": xops,
-                                            "pair_terms_per_launch": apairs, "pair_terms_evaluated": xnear,
-                                            "all_pairs_equivalent_tflops": aops / (bkm * 1e-3) / 1e12}}
-    log("fwd+bwd: %.3f ms/rollout (adjoint kernel %.3f ms)" % (fbms, bms / max(bl, 1)))
+                      "backward_kernel_ms": bkm, "controlled": "all objects", "checkpoint_every": 10,
+                      "backward_roofline": adjoint_roofline(alg, alg_pairs, xops, xnear, bkm)}
+    log("fwd+bwd: %.3f ms/rollout (adjoint kernel %.3f ms, %.1f%% of FP32 by the method's count)" % (
+        fbms, bkm, 100 * out["fwd_bwd"]["backward_roofline"]["frac"]))
+    del a, k, fmet
 
-    observation(out, scene, ds, dev, traj2, reps)
-
+    observation(out, scene, ds, dev, fused_traj, reps)
+    closed_loop(out, scene, ds, dev, fused_ms)
+    step_latency(out, dev)
     ragged(out, dev)
     idm(out, scene, ds, dev, tune)
     fwd_bwd_config3(out, dev)
+    config4(out, dev)
+
+
+def closed_loop(out, scene, ds, dev, fused_ms, E=8, K=1000):
+    """Closed-loop simulation of the bench workload: 80 calls of
+    wm_step_observe (dynamics, every metric, then the successor's default
+    observation for 8 egos per scenario, k = 1000, with road and object
+    features), captured as one HIP graph; per-step latency and the cost
+    against the fused rollout of the same 80 steps (which has no
+    observation)."""
+    import torch
+    from paper_2310_08710_amd import wm
+    S, n, T = scene.num_scenarios, scene.total_objects, scene.steps
+    maxN = ds.batch.max_objects
+    traj = wm.State.empty((T, n), dev)
+    met = wm.Metrics.empty((T, n), dev)
+    idx = torch.empty((S * E * K,), dtype=torch.int32, device=dev)
+    rf = torch.empty((S * E * K * 4,), device=dev)
+    of = torch.empty((S * E * maxN * 8,), device=dev)
+    ws = ds.batch.workspace()
+    wm.roadgraph_prepare(ds.batch, ds.rg, ws)
+    acts = [wm.Action(ds.act_seq.accel[t], ds.act_seq.curvature[t], ds.act_seq.controlled) for t in range(T)]
+
+    def loop():
+        c = ds.init
+        for t in range(1, T + 1):
+            wm.step_observe(ds.batch, c, acts[t - 1], ds.log_seq.row(t), ds.rg, scene.dt, traj.row(t - 1),
+                            met.row(t - 1), ws, ds.ego, E, K, idx, rf, of)
+            c = traj.row(t - 1)
+
+    ms = _time_graph(loop, 3)
+    out["closed_loop"] = {"ms_per_rollout": ms, "ms_per_step": ms / T, "unit": "agent-steps/s",
+                          "value": n * T / (ms * 1e-3), "ego_observations_per_s": S * E * T / (ms * 1e-3),
+                          "vs_fused_rollout": ms / fused_ms,
+                          "workload": "80 x wm_step_observe on the bench workload (every metric, then 8 egos per "
+                                      "scenario, k = 1000, road and object features), one HIP graph"}
+    log("closed loop: %.3f ms per 80 steps (%.3f ms/step, %.2fx the fused rollout)" % (ms, ms / T, ms / fused_ms))
+
+
+def step_latency(out, dev, reps=50):
+    """Per-step latency of the plain step on a prepared road graph (one HIP
+    graph replay per step): transition only and transition + every metric,
+    for the 1 x 16-object scene and for 1 and 16 scenarios of 128 objects with
+    30,000 road points (the paper's Step / Transition / Metrics rows at batch
+    1 and 16); plus the 80-step expert rollout at those batches."""
+    import torch
+    from paper_2310_08710_amd import synth, wm
+    res = {}
+    for key, cfg, S in (("config0_1x16", 0, None), ("bs1_128", 1, 1), ("bs16_128", 1, 16)):
+        sc = synth.make_scene(cfg, scenarios=S)
+        ds = wm.upload(sc, dev)
+        n, T = sc.total_objects, sc.steps
+        ws = ds.batch.workspace()
+        wm.roadgraph_prepare(ds.batch, ds.rg, ws)
+        act = wm.Action(ds.act_seq.accel[0], ds.act_seq.curvature[0], ds.act_seq.controlled)
+        nxt = wm.State.empty(n, dev)
+        met = wm.Metrics.empty(n, dev)
+        tr = _time_graph(lambda: wm.step_prepared(ds.batch, ds.init, act, ds.log_seq.row(1), None, sc.dt, nxt, None,
+                                                  ws), reps, median=True)
+        st = _time_graph(lambda: wm.step_prepared(ds.batch, ds.init, act, ds.log_seq.row(1), ds.rg, sc.dt, nxt, met,
+                                                  ws), reps, median=True)
+        wsr = ds.batch.workspace(T, 0)
+        traj = wm.State.empty((T, n), dev)
+        mets = wm.Metrics.empty((T, n), dev)
+        ro = _time_graph(lambda: wm.rollout(ds.batch, ds.init, ds.act_seq, ds.log_seq, ds.rg, T, sc.dt, wsr, traj=traj,
+                                            metrics=mets), 5, median=True)
+        res[key] = {"scenarios": sc.num_scenarios, "objects": n, "rg_points_per_scenario": int(sc.rg_off[1]),
+                    "transition_ms": tr, "step_ms": st, "metrics_ms": st - tr,
+                    "step_agent_steps_per_s": n / (st * 1e-3), "rollout_steps": T, "rollout_ms": ro}
+        log("step latency %s: transition %.4f ms, step + metrics %.4f ms, %d-step rollout %.3f ms" % (
+            key, tr, st, T, ro))
+    out["step_latency"] = res
+
+
+def config4(out, dev, reps=3, E=8, K=1000):
+    """4,096 ragged scenarios (objects U{32..128}, road points U{10000..30000}):
+    the default observation of 8 egos per scenario (32,768 egos, k = 1000),
+    then the 80-step fused rollout with every metric, loss and checkpoints
+    every 10 steps plus the adjoint (RolloutLoss forward + backward), 8
+    controlled objects per scenario."""
+    import torch
+    from paper_2310_08710_amd import synth, wm
+    t = time.perf_counter()
+    sc = synth.make_scene(4)
+    ds = wm.upload(sc, dev)
+    log("config 4 scene: %d scenarios, %d objects, %d road points (%.1f s)" % (
+        sc.num_scenarios, sc.total_objects, sc.total_rg_points, time.perf_counter() - t))
+    S, n, T = sc.num_scenarios, sc.total_objects, sc.steps
+    oms, oroof, bufs = observe_once(sc, ds, dev, ds.init, reps, E, K)
+    del bufs
+    a = ds.act_seq.accel.clone().requires_grad_(True)
+    k = ds.act_seq.curvature.clone().requires_grad_(True)
+    fmet = wm.Metrics.empty((T, n), dev)
+
+    def fb():
+        a.grad = None
+        k.grad = None
+        L = wm.RolloutLoss.apply(a, k, ds.batch, ds.init, ds.act_seq.controlled, ds.log_seq, ds.rg, T, sc.dt, 10, fmet)
+        L.sum().backward()
+
+    fb()
+    torch.cuda.synchronize()
+    wm.profile_enable(True)
+    wm.profile_collect(wm.PROF_BACKWARD)
+    wm.profile_collect(wm.PROF_ROLLOUT)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fb()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    bms, bl = wm.profile_collect(wm.PROF_BACKWARD)
+    fms, fl = wm.profile_collect(wm.PROF_ROLLOUT)
+    wm.profile_enable(False)
+    bkm, fkm = bms / max(bl, 1), fms / max(fl, 1)
+    valid = int(sc.log["valid"][synth.T0].sum())
+    fops, _ = rollout_ops(sc, T)
+    alg, alg_pairs = adjoint_algorithmic_ops(sc.obj_off, sc.controlled, sc.log["valid"][synth.T0], T)
+    out["config4"] = {
+        "workload": "4096 ragged scenarios, objects U{32..128}, road points U{10000..30000}, 8 egos and 8 controlled "
+                    "objects per scenario, k = 1000, 80 steps, checkpoint every 10",
+        "observe": {"ms": oms, "egos": S * E, "egos_per_s": S * E / (oms * 1e-3), "roofline": oroof},
+        "fwd_bwd": {"value": S * T / (ms * 1e-3), "unit": "rollout scenario-steps/s",
+                    "agent_steps_per_s": valid * T / (ms * 1e-3), "ms_per_rollout": ms,
+                    "forward_kernel_ms": fkm, "forward_roofline_frac": fops / (fkm * 1e-3) / PEAK_FP32,
+                    "backward_kernel_ms": bkm,
+                    "backward_roofline": adjoint_roofline(alg, alg_pairs, None, None, bkm)},
+        "observe_plus_fwd_bwd_ms": oms + ms}
+    log("config 4: observe %.3f ms (%.1f%% of HBM), fwd+bwd %.3f ms/rollout (forward kernel %.3f ms, adjoint %.3f ms)"
+        % (oms, 100 * oroof["frac"], ms, fkm, bkm))
 
 
 def fwd_bwd_config3(out, dev, reps=3):
@@ -531,12 +777,10 @@ def fwd_bwd_config3(out, dev, reps=3):
         fms, fl = wm.profile_collect(wm.PROF_ROLLOUT)
         wm.profile_enable(False)
         bkm = bms / max(bl, 1)
-        aops, _ = adjoint_ops(sc, sc.controlled)
+        alg, alg_pairs = adjoint_algorithmic_ops(sc.obj_off, sc.controlled, sc.log["valid"][synth.T0], T)
         res[key] = {"value": S * T / (ms * 1e-3), "agent_steps_per_s": sc.total_objects * T / (ms * 1e-3),
                     "ms_per_rollout": ms, "forward_kernel_ms": fms / max(fl, 1), "backward_kernel_ms": bkm,
-                    "backward_tflops": xops / (bkm * 1e-3) / 1e12, "backward_frac": xops / (bkm * 1e-3) / PEAK_FP32,
-                    "pair_terms_evaluated": xnear,
-                    "all_pairs_equivalent_tflops": aops / (bkm * 1e-3) / 1e12}
+                    "backward_roofline": adjoint_roofline(alg, alg_pairs, xops, xnear, bkm)}
         log("fwd+bwd (512 x 128, 8 controlled, %s): %.3f ms/rollout (forward kernel %.3f ms, adjoint %.3f ms)" % (
             key, ms, fms / max(fl, 1), bms / max(bl, 1)))
     res["value"] = res["full_metrics"]["value"]
@@ -606,8 +850,9 @@ def idm(out, scene, ds, dev, tune):
     log("IDM rollout: %.3f ms (playback of the same objects %.3f ms)" % (ims, pms))
 
 
-def _time_graph(fn, reps):
-    """Capture fn() as one HIP graph and return the mean wall time of a replay [ms]."""
+def _time_graph(fn, reps, median=False):
+    """Capture fn() as one HIP graph and return the mean wall time of a replay
+    [ms], or with `median` the median of HIP-event times of single replays."""
     import torch
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -619,11 +864,21 @@ def _time_graph(fn, reps):
         fn()
     g.replay()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g.replay()
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / reps
+    if median:
+        stream = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for i in range(reps):
+            g.replay()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]))
+    else:
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
     del g
     return ms
 

@@ -283,6 +283,20 @@ int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
 int wm_observe_seq(const wm_batch *batch, const wm_state *st, int32_t T, const wm_roadgraph *rg, const int32_t *ego,
                    int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream);
 
+/* One closed-loop simulator step (Sec. 4.1: step returns the successor
+ * state, its metrics and the next observation): wm_step_prepared followed by
+ * wm_observe of the successor `next` (the default observation of Sec. 3.2 for
+ * the E egos of every scenario), in one call, with no host synchronization,
+ * so that a policy loop can capture it in a HIP graph.  Arguments and outputs
+ * as in those two calls: rg is required (the observation reads it); off-road
+ * metrics read the road edges that wm_roadgraph_prepare compacted into `ws`
+ * (same precondition as wm_step_prepared).  Every host-visible argument of
+ * both parts is validated before the first launch. */
+int wm_step_observe(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+                    const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *metrics, const int32_t *ego,
+                    int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *ws,
+                    size_t ws_bytes, void *stream);
+
 /* Fused rollout of T steps (Sec. 5.1 Rollout; each step as wm_step with all
  * metrics, evaluated on the successor state).  One persistent kernel runs all
  * T steps of every (scenario, object slice) work unit, taking units from a

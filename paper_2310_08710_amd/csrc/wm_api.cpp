@@ -471,11 +471,9 @@ int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
     return device_status("wm_offroad");
 }
 
-int wm_observe_seq(const wm_batch *batch, const wm_state *st, int32_t T, const wm_roadgraph *rg, const int32_t *ego,
-                   int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream)
+static int observe_checks(const wm_batch *batch, const wm_roadgraph *rg, const int32_t *ego, int32_t E, int32_t k,
+                          int32_t T, const int32_t *rg_idx)
 {
-    CHECK(check_batch(batch));
-    CHECK(check_state(st, "state"));
     if (!rg)
         return fail(WM_ERR_NULL, "roadgraph is NULL");
     CHECK(check_rg(rg));
@@ -492,6 +490,15 @@ int wm_observe_seq(const wm_batch *batch, const wm_state *st, int32_t T, const w
     const long long slots = (long long)batch->num_scenarios * E;
     if (slots * T * (k > 8 ? k : 8) > 0x7fffffffLL || slots * T * batch->max_objects * 8 > 0x7fffffffLL * 4)
         return fail(WM_ERR_UNSUPPORTED, "T * S * E * k too large");
+    return WM_OK;
+}
+
+int wm_observe_seq(const wm_batch *batch, const wm_state *st, int32_t T, const wm_roadgraph *rg, const int32_t *ego,
+                   int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream)
+{
+    CHECK(check_batch(batch));
+    CHECK(check_state(st, "state"));
+    CHECK(observe_checks(batch, rg, ego, E, k, T, rg_idx));
     wm::ObserveArgs a{batch->obj_off, batch->rg_off, *st, *rg, ego, E, k, batch->max_objects, rg_idx, rg_feat,
                       obj_feat, (long)batch->total_objects, (long)batch->num_scenarios};
     {
@@ -505,6 +512,24 @@ int wm_observe(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
                int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *stream)
 {
     return wm_observe_seq(batch, st, 1, rg, ego, E, k, rg_idx, rg_feat, obj_feat, stream);
+}
+
+int wm_step_observe(const wm_batch *batch, const wm_state *cur, const wm_action *act, const wm_state *log_next,
+                    const wm_roadgraph *rg, float dt, wm_state *next, wm_metrics *metrics, const int32_t *ego,
+                    int32_t E, int32_t k, int32_t *rg_idx, float *rg_feat, float *obj_feat, void *ws,
+                    size_t ws_bytes, void *stream)
+{
+    // every host-visible check of both parts runs before the first launch
+    CHECK(check_batch(batch));
+    CHECK(observe_checks(batch, rg, ego, E, k, 1, rg_idx));
+    CHECK(step_impl(batch, cur, act, log_next, rg, dt, next, metrics, ws, ws_bytes, stream, StepWs::Prepared));
+    wm::ObserveArgs a{batch->obj_off, batch->rg_off, *next, *rg, ego, E, k, batch->max_objects, rg_idx, rg_feat,
+                      obj_feat, (long)batch->total_objects, (long)batch->num_scenarios};
+    {
+        ProfScope ps(WM_PROF_OBSERVE, (hipStream_t)stream);
+        wm::launch_observe(*batch, a, 1, (hipStream_t)stream);
+    }
+    return device_status("wm_step_observe");
 }
 
 static int rollout_checks(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,

@@ -97,6 +97,9 @@ def lib() -> C.CDLL:
                               C.POINTER(CRoadgraph), C.c_float, C.POINTER(CState), C.POINTER(CMetrics), _P,
                               C.c_size_t, _P]
         L.wm_step_prepared.argtypes = L.wm_step.argtypes
+        L.wm_step_observe.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
+                                      C.POINTER(CRoadgraph), C.c_float, C.POINTER(CState), C.POINTER(CMetrics), _P,
+                                      C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_size_t, _P]
         L.wm_step_noalloc.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
                                       C.POINTER(CRoadgraph), C.c_float, C.POINTER(CState), C.POINTER(CMetrics), _P]
         L.wm_roadgraph_prepare.argtypes = [C.POINTER(CBatch), C.POINTER(CRoadgraph), _P, C.c_size_t, _P]
@@ -353,6 +356,25 @@ def step_prepared(batch: Batch, cur: State, act: Action, log_next: State, rg: Op
                   nxt: State, metrics: Optional[Metrics], ws: torch.Tensor, stream=None):
     """step() reusing the edges that roadgraph_prepare() compacted into `ws`."""
     _step(lib().wm_step_prepared, batch, cur, act, log_next, rg, dt, nxt, metrics, ws, stream)
+
+
+def step_observe(batch: Batch, cur: State, act: Action, log_next: State, rg: Roadgraph, dt: float, nxt: State,
+                 metrics: Optional[Metrics], ws: Optional[torch.Tensor], ego: torch.Tensor, E: int, k: int,
+                 rg_idx: torch.Tensor, rg_feat: Optional[torch.Tensor] = None, obj_feat: Optional[torch.Tensor] = None,
+                 stream=None):
+    """One closed-loop step: step_prepared() then observe() of the successor
+    `nxt`, in one library call (off-road metrics read the edges that
+    roadgraph_prepare() compacted into `ws`)."""
+    N = batch.total_objects
+    b, c, a, l, n = batch.c(), cur.c(N, "cur"), act.c(N, N), log_next.c(N, "log_next"), nxt.c(N, "next")
+    r = rg.c(batch.total_rg_points)
+    m = metrics.c(N) if metrics is not None else None
+    _observe_sizes(batch, 1, ego, E, k, rg_idx, rg_feat, obj_feat)
+    _need(ws, 0, torch.uint8, "ws")
+    _check(lib().wm_step_observe(C.byref(b), C.byref(c), C.byref(a), C.byref(l), C.byref(r), dt, C.byref(n),
+                                 C.byref(m) if m is not None else None, ego.data_ptr(), E, k, rg_idx.data_ptr(),
+                                 _ptr(rg_feat), _ptr(obj_feat), _ptr(ws), ws.numel() if ws is not None else 0,
+                                 _stream(stream)))
 
 
 def inverse_action(batch: Batch, cur: State, nxt: State, dt: float, accel: torch.Tensor, curvature: torch.Tensor,

@@ -123,6 +123,34 @@ def test_step_noalloc_validation():
     assert "wm_step_noalloc" in _msg() and "scratch" in _msg()
 
 
+def test_step_observe_validation():
+    """The closed-loop step validates the step's and the observation's
+    arguments before any launch."""
+    lib = wm.lib()
+    m = wm.CMetrics(FAKE, FAKE, None, None, None)
+
+    def call(batch=None, cur=None, rg="fake", ego=FAKE, E=8, k=100, idx=FAKE, dt=0.1, ws=FAKE, ws_bytes=1 << 30):
+        b = batch if batch is not None else _batch()
+        c = cur if cur is not None else _state()
+        r = _rg() if rg == "fake" else rg
+        return lib.wm_step_observe(C.byref(b), C.byref(c), C.byref(_act()), C.byref(_state()),
+                                   C.byref(r) if r is not None else None, dt,
+                                   C.byref(wm.CState(*([FAKE + 64] * 8))), C.byref(m), ego, E, k, idx, None, None,
+                                   ws, ws_bytes, None)
+
+    assert call(rg=None) == wm.WM_ERR_NULL
+    assert call(ego=None) == wm.WM_ERR_NULL
+    assert call(idx=None) == wm.WM_ERR_NULL
+    assert call(E=0) == wm.WM_ERR_RANGE
+    assert call(k=0) == wm.WM_ERR_RANGE
+    assert call(k=2000) == wm.WM_ERR_UNSUPPORTED
+    assert call(batch=wm.CBatch(1, 10, 40000, 10, 40000, FAKE, FAKE)) == wm.WM_ERR_UNSUPPORTED   # > 32768 points
+    assert call(cur=_state(null_field=0)) == wm.WM_ERR_NULL
+    assert call(dt=-1.0) == wm.WM_ERR_RANGE
+    assert call(ws=None) == wm.WM_ERR_WORKSPACE                      # off-road metrics read the prepared edges
+    assert call(ws_bytes=8) == wm.WM_ERR_WORKSPACE
+
+
 def test_offroad_and_tuning_validation():
     L = wm.lib()
     b, s, r = _batch(), _state(), _rg()

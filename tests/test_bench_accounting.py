@@ -60,3 +60,25 @@ def test_uncontrolled_objects_come_from_the_log():
     ctrl = torch.tensor([1, 0], dtype=torch.uint8)
     _, near, _ = bench.adjoint_executed_ops(off, ctrl, init, log, traj, T)
     assert near == T - 1
+
+
+def test_algorithmic_adjoint_pairs():
+    """The method's count of the adjoint's pairs: unordered pairs of valid
+    objects with a controlled member, 8 x 127 - 28 = 988 per step at 128
+    objects with 8 controlled; invalid objects take part in none."""
+    off = np.array([0, 128, 256], np.int32)
+    ctrl = np.zeros(256, np.uint8)
+    ctrl[0:8] = 1
+    ctrl[128:136] = 1
+    valid = np.ones(256, np.uint8)
+    ops, pairs = bench.adjoint_algorithmic_ops(off, ctrl, valid, 80)
+    assert pairs == 2 * 988 * 80
+    assert ops == bench.ADJ_ALG_OPS_PER_PAIR * pairs
+    # every object controlled: all N (N - 1) / 2 pairs
+    _, pairs = bench.adjoint_algorithmic_ops(off[:2], np.ones(128, np.uint8), valid[:128], 1)
+    assert pairs == 128 * 127 // 2
+    # an invalid controlled object and an invalid partner drop out
+    valid[0] = 0
+    valid[100] = 0
+    _, pairs = bench.adjoint_algorithmic_ops(off[:2], ctrl[:128], valid[:128], 1)
+    assert pairs == 7 * 125 - 21          # 126 valid objects, 7 of them controlled
