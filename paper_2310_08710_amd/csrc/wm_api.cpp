@@ -689,7 +689,8 @@ int wm_rollout_backward(const wm_batch *batch, const wm_state *init, const wm_ac
     a.dloss = dloss;
     a.grad_a = grad_accel;
     a.grad_k = grad_curvature;
-    a.seg = (float *)((unsigned char *)ws + L.seg);
+    a.rec = (float *)((unsigned char *)ws + L.seg);
+    a.part = a.rec + (size_t)wm::kRecFields * T * batch->total_objects;
     {
         ProfScope ps(WM_PROF_BACKWARD, (hipStream_t)stream);
         wm::launch_backward(a, (hipStream_t)stream);

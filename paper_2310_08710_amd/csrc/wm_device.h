@@ -31,6 +31,29 @@ struct ObjLds {
 //   v = |(vx, vy)|; x' = x + vx dt + a cos(yaw) dt^2/2; y' likewise with sin;
 //   yaw' = yaw + kappa (v dt + a dt^2/2); v' = v + a dt; (vx', vy') = v'(cos, sin)(yaw')
 // ---------------------------------------------------------------------------
+// The same step, also returning the sine and cosine of the yaw before (s, c)
+// and after (ns, nc) it, which the adjoint's factors reuse.
+__device__ __forceinline__ void bicycle_forward_sc(float &x, float &y, float &yaw, float &vx, float &vy,
+                                                   float a, float k, float dt, float &s, float &c, float &ns,
+                                                   float &nc)
+{
+    const float hdt2 = 0.5f * dt * dt;
+    const float v = sqrtf(__builtin_fmaf(vy, vy, vx * vx));
+    sincosf(yaw, &s, &c);
+    const float ahdt2 = a * hdt2;
+    const float nx = x + __builtin_fmaf(vx, dt, ahdt2 * c);
+    const float ny = y + __builtin_fmaf(vy, dt, ahdt2 * s);
+    const float dist = __builtin_fmaf(v, dt, ahdt2);
+    const float nyaw = __builtin_fmaf(k, dist, yaw);
+    const float nv = __builtin_fmaf(a, dt, v);
+    sincosf(nyaw, &ns, &nc);
+    x = nx;
+    y = ny;
+    yaw = nyaw;
+    vx = nv * nc;
+    vy = nv * ns;
+}
+
 __device__ __forceinline__ void bicycle_forward(float &x, float &y, float &yaw, float &vx, float &vy,
                                                 float a, float k, float dt)
 {

@@ -107,7 +107,7 @@ struct ObserveArgs {
 
 struct BackwardArgs {
     int S, n, T, K, maxN;
-    int SB;          // steps per LDS block (backward_block_steps)
+    int SB;          // steps per pair work-group (backward_block_steps)
     float dt;
     const int32_t *obj_off;
     wm_state init;
@@ -116,8 +116,12 @@ struct BackwardArgs {
     wm_state ckpt;
     const float *dloss;
     float *grad_a, *grad_k;
-    float *seg;      // [K+1][5][n] recomputed segment states (x, y, yaw, vx, vy)
+    float *rec;      // [T][n][kRecFields] the reverse recursion's inputs per step and object
+    float *part;     // [T][n][4] pair-term sums per step and controlled object
 };
+
+// Workspace rows of the adjoint's recursion inputs per step and object.
+constexpr int kRecFields = 16;
 
 // Workspace sections (byte offsets, each 256-aligned).
 struct WsLayout {
@@ -139,7 +143,7 @@ inline WsLayout ws_layout(int S, int n, int P, int T, int K)
     L.units = take(sizeof(int32_t) * 2 * ((size_t)n + 1));
     L.lossp = take(sizeof(float) * ((size_t)n + 1));
     L.counter = take(sizeof(int32_t) * 16);
-    L.seg = (T > 0 && K > 0) ? take(sizeof(float) * 5 * (size_t)(K + 1) * (size_t)n) : o;
+    L.seg = (T > 0 && K > 0) ? take(sizeof(float) * (kRecFields + 4) * (size_t)T * (size_t)n) : o;
     L.idmP = T > 0 ? take(sizeof(float) * 4 * (size_t)(T + 1) * (size_t)n) : o;
     L.idmA = T > 0 ? take((size_t)n + 1) : o;
     L.total = o;

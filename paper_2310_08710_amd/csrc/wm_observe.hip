@@ -543,6 +543,7 @@ constexpr int kBoundChunk = kFastThreads * kPtsPerThread;
 constexpr int kBoundGroups = 4;                                     // bounding pass: groups loaded at once
 static_assert(kBlockPts / kPtsPerThread == 4, "four threads per block");
 constexpr int kGroupsPerPass = kFastThreads / kBlockPts;            // candidate blocks per round
+constexpr int kBlockMinRows = 4;                                    // rows per ego for the block-pruned form
 constexpr int kScanRounds = 16;                                     // rounds loaded at once, keys kept
 constexpr int kRankPerThread = WM_MAX_TOPK / kFastThreads;          // keys below bin b per thread (c_less < 1024)
 
@@ -1095,6 +1096,20 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3)
     }
 }
 
+// Every work item with the exact selection, one 1024-thread work-group per
+// item: the form for few rows per ego (one state row), where the
+// block-pruned kernel would bound a scenario's blocks for one or two
+// observations.  Work-groups are dispatched to the eight XCDs in turn; each
+// XCD takes a contiguous range of items, so the egos of one scenario share
+// that XCD's L2 copy of its road graph.
+__global__ __launch_bounds__(kObsThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_observe_each(ObserveArgs A,
+                                                                                                        int rows)
+{
+    const long W = (long)rows * A.S * A.E;
+    const long p = blockIdx.x, full = W / 8 * 8;
+    observe_exact_item(A, rows, p < full ? (p % 8) * (W / 8) + p / 8 : p);
+}
+
 // The egos the block-pruned kernel marked (rg_idx of their first place set to
 // kHandOver) get the exact selection over every point: each work-group reads
 // the marks of 1024 consecutive work items and runs the marked ones in turn.
@@ -1155,9 +1170,13 @@ void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream
     // work-group takes as many observations as leave about four work-groups
     // per resident slot: consecutive rows of one ego, or, with fewer rows
     // than that, all rows of several egos.
-    const long slots = observe_slots();
     const long S = b.num_scenarios;
     const long items = (long)rows * S * a.E;
+    if (rows < kBlockMinRows) {
+        hipLaunchKernelGGL(k_observe_each, dim3((unsigned)items), dim3(kObsThreads), 0, st, a, rows);
+        return;
+    }
+    const long slots = observe_slots();
     long per = items / (4 * slots);
     if (per < 1)
         per = 1;

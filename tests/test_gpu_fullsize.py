@@ -190,6 +190,28 @@ def test_config4_observation_full_size(config4):
         d = go[s][..., 2] - oof[0][..., 2]
         ok[..., 2] = np.abs(d - 2 * np.pi * np.round(d / (2 * np.pi))) <= 1e-5
         assert ok.all()
+    # the block-pruned form: logged rows 0..3 in one call (each row's bound
+    # from the previous one), sampled scenarios against the oracle
+    del idx, rf, of
+    R = 4
+    idx = torch.empty((R, S * E * K), dtype=torch.int32, device=dev)
+    rf = torch.empty((R, S * E * K * 4), device=dev)
+    wm.observe_seq(ds.batch, ds.log_seq, R, ds.rg, ds.ego, E, K, idx, rf, None)
+    torch.cuda.synchronize()
+    lw = sc.log_window()
+    for r in range(R):
+        gi = idx[r].cpu().numpy().reshape(S, E, K)
+        gr = rf[r].cpu().numpy().reshape(S, E, K, 4)
+        for s in (7, 2047, 4094):
+            o0, o1 = sc.obj_off[s], sc.obj_off[s + 1]
+            p0, p1 = sc.rg_off[s], sc.rg_off[s + 1]
+            sub_st = f64({q: v[r, o0:o1] for q, v in lw.items()})
+            sub_rg = f64({q: v[p0:p1] for q, v in sc.rg.items()})
+            ego = (sc.ego[s] - o0).reshape(1, E)
+            oi, orf, _ = oracle.observe(np.array([0, o1 - o0], np.int32), np.array([0, p1 - p0], np.int32), sub_st,
+                                        sub_rg, ego, K, maxN)
+            np.testing.assert_array_equal(gi[s], oi[0], err_msg="row %d scenario %d" % (r, s))
+            assert within(gr[s], orf[0]).all()
 
 
 def test_config4_adjoint_full_size(config4):

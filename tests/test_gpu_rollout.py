@@ -255,6 +255,32 @@ def test_adjoint_many_objects():
     assert np.abs(oga).max() > 0.1
 
 
+def _observe_both(ds, st, rg, E, k, obj=False, rows=4):
+    """The observation of one state row `st` (a State of [n]) through both
+    forms: wm_observe (one row: one work-group per ego over every point) and
+    wm_observe_seq over `rows` copies of the row (the block-pruned form, whose
+    later rows start from the previous row's bound).  Returns (rg_idx,
+    rg_feat, obj_feat or None) as numpy arrays, once per row of each form."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = st.x.device
+    S, maxN = ds.batch.num_scenarios, ds.batch.max_objects
+    slots = S * E
+    idx = torch.empty((rows, slots * k), dtype=torch.int32, device=dev)
+    rf = torch.empty((rows, slots * k * 4), device=dev)
+    of = torch.empty((rows, slots * maxN * 8), device=dev) if obj else None
+    wm.observe(ds.batch, st, rg, ds.ego, E, k, idx[0], rf[0], of[0] if obj else None)
+    torch.cuda.synchronize()
+    out = [(idx[0].cpu().numpy().copy(), rf[0].cpu().numpy().copy(), of[0].cpu().numpy().copy() if obj else None)]
+    rep = wm.State(*[getattr(st, f).reshape(1, -1).repeat(rows, 1).contiguous()
+                     for f in wm.STATE_FIELDS + ("valid",)])
+    wm.observe_seq(ds.batch, rep, rows, rg, ds.ego, E, k, idx, rf, of)
+    torch.cuda.synchronize()
+    for r in range(rows):
+        out.append((idx[r].cpu().numpy(), rf[r].cpu().numpy(), of[r].cpu().numpy() if obj else None))
+    return out
+
+
 @pytest.mark.parametrize("k", [1, 64, 333, 1024])
 def test_observe_topk_and_frames(k):
     import torch
@@ -268,19 +294,15 @@ def test_observe_topk_and_frames(k):
     ds = wm.upload(sc, dev)
     S, E = sc.num_scenarios, sc.ego.shape[1]
     maxN = ds.batch.max_objects
-    idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
-    rf = torch.empty((S * E * k * 4,), device=dev)
-    of = torch.empty((S * E * maxN * 8,), device=dev)
-    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, k, idx, rf, of)
-    torch.cuda.synchronize()
     st = sc.state_at(synth.T0)
     o_idx, o_rf, o_of = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, maxN)
-    np.testing.assert_array_equal(idx.cpu().numpy().reshape(S, E, k), o_idx)     # bit-exact
-    assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all()
-    g_of = of.cpu().numpy().reshape(S, E, maxN, 8)
-    ok = within(g_of, o_of)
-    ok[..., 2] = np.abs(((g_of[..., 2] - o_of[..., 2] + math.pi) % (2 * math.pi)) - math.pi) <= 1e-5
-    assert ok.all()
+    for gi, grf, gof in _observe_both(ds, ds.init, ds.rg, E, k, obj=True):
+        np.testing.assert_array_equal(gi.reshape(S, E, k), o_idx)     # bit-exact
+        assert within(grf.reshape(S, E, k, 4), o_rf).all()
+        g_of = gof.reshape(S, E, maxN, 8)
+        ok = within(g_of, o_of)
+        ok[..., 2] = np.abs(((g_of[..., 2] - o_of[..., 2] + math.pi) % (2 * math.pi)) - math.pi) <= 1e-5
+        assert ok.all()
 
 
 @pytest.mark.parametrize("k", [1000, 1024])
@@ -315,17 +337,13 @@ def test_observe_selection_inside_one_bin(k):
     ds = wm.upload(sc, dev)
     S, E = sc.num_scenarios, sc.ego.shape[1]
     maxN = ds.batch.max_objects
-    idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
-    rf = torch.empty((S * E * k * 4,), device=dev)
-    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, k, idx, rf, None)
-    torch.cuda.synchronize()
     o_idx, o_rf, _ = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, maxN)
-    gi = idx.cpu().numpy().reshape(S, E, k)
     # the constructed groups do decide the k-th place of ego 0
     for s in range(S):
         assert (o_idx[s, 0] >= 0).all()
-    np.testing.assert_array_equal(gi, o_idx)     # bit-exact
-    assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all()
+    for gi, grf, _ in _observe_both(ds, ds.init, ds.rg, E, k):
+        np.testing.assert_array_equal(gi.reshape(S, E, k), o_idx)     # bit-exact
+        assert within(grf.reshape(S, E, k, 4), o_rf).all()
 
 
 def test_observe_when_the_sampled_bound_misleads():
@@ -350,15 +368,12 @@ def test_observe_when_the_sampled_bound_misleads():
         sc.rg["valid"][p0:p1] = 1
     ds = wm.upload(sc, dev)
     S, E, k = sc.num_scenarios, sc.ego.shape[1], 1000
-    idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
-    rf = torch.empty((S * E * k * 4,), device=dev)
-    wm.observe(ds.batch, ds.init, ds.rg, ds.ego, E, k, idx, rf, None)
-    torch.cuda.synchronize()
     o_idx, o_rf, _ = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, ds.batch.max_objects)
     # ego 0 sees its 500-odd near points first, then far ones
     assert ((o_idx[:, 0, :400] % 16) == 0).all() and ((o_idx[:, 0, -100:] % 16) != 0).any()
-    np.testing.assert_array_equal(idx.cpu().numpy().reshape(S, E, k), o_idx)
-    assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all()
+    for gi, grf, _ in _observe_both(ds, ds.init, ds.rg, E, k):
+        np.testing.assert_array_equal(gi.reshape(S, E, k), o_idx)
+        assert within(grf.reshape(S, E, k, 4), o_rf).all()
 
 
 def test_observe_small_and_odd_point_counts():
@@ -397,12 +412,9 @@ def test_observe_small_and_odd_point_counts():
     for k in (4, 1000):
         o_idx, o_rf, _ = oracle.observe(sc.obj_off, sc.rg_off, f64(st), f64(sc.rg), sc.ego, k, maxN)
         for rg in (ds.rg, rg_odd):
-            idx = torch.empty((S * E * k,), dtype=torch.int32, device=dev)
-            rf = torch.empty((S * E * k * 4,), device=dev)
-            wm.observe(ds.batch, ds.init, rg, ds.ego, E, k, idx, rf, None)
-            torch.cuda.synchronize()
-            np.testing.assert_array_equal(idx.cpu().numpy().reshape(S, E, k), o_idx, err_msg="k=%d" % k)
-            assert within(rf.cpu().numpy().reshape(S, E, k, 4), o_rf).all(), k
+            for gi, grf, _ in _observe_both(ds, ds.init, rg, E, k):
+                np.testing.assert_array_equal(gi.reshape(S, E, k), o_idx, err_msg="k=%d" % k)
+                assert within(grf.reshape(S, E, k, 4), o_rf).all(), k
 
 
 def test_observe_every_step_of_a_sequence():
