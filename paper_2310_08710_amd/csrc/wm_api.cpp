@@ -578,8 +578,10 @@ static int rollout_impl(const wm_batch *batch, const wm_state *init, const wm_ac
     // (force_off: the autotuner times the scan without outputs)
     const bool want_off =
         rg && (force_off || (met_seq && (met_seq->offroad || met_seq->offroad_margin || met_seq->reward)));
-    if (want_off)
+    if (want_off) {
         wm::launch_compact_edges(*batch, *rg, w, L, s);
+        wm::launch_edge_boxes(*batch, w, L, s);
+    }
     wm::launch_build_units(*batch, 64 * tn.CW, want_off ? (const int32_t *)(w + L.ecount) : nullptr, w, L, s);
     wm::RollArgs a{};
     a.S = batch->num_scenarios;

@@ -384,6 +384,140 @@ __device__ __forceinline__ void scan_edges(const float *__restrict__ stream, int
     }
 }
 
+// Lower bound of D = fl(fl(dx^2) + dy^2) (edge_d2) over the points of a box
+// (xmin, xmax, ymin, ymax) for the corner (cx, cy): the box's nearest point,
+// with the same roundings.  Rounding is monotone, so for every point q of
+// the box |fl(qx - cx)| >= the bound's dx (likewise y) and D(q) >= the
+// bound, bit for bit.  An empty box (+inf, -inf, ...) gives +inf.
+__device__ __forceinline__ float box_lb(const float4 bb, float cx, float cy)
+{
+    const float lx = bb.x - cx, hx = bb.y - cx, ly = bb.z - cy, hy = bb.w - cy;
+    const float dx = lx > 0.f ? lx : (hx < 0.f ? -hx : 0.f);
+    const float dy = ly > 0.f ? ly : (hy < 0.f ? -hy : 0.f);
+    return __builtin_fmaf(dy, dy, dx * dx);
+}
+
+// Minimum of T over the 32 points of block sb (0..3) of a chunk staged in
+// LDS, folded into m: fold_chunk restricted to that block.
+template <int R>
+__device__ __forceinline__ void fold_block(const float4 *stage, int sb, const float (&m2x)[R],
+                                           const float (&m2y)[R], float (&m)[R])
+{
+#pragma unroll 4
+    for (int j4 = 8 * sb; j4 < 8 * sb + 8; ++j4) {
+        const float4 X = stage[j4], Y = stage[kChunk / 4 + j4], Q = stage[kChunk / 2 + j4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float t0 = __builtin_fmaf(m2y[r], Y.x, __builtin_fmaf(m2x[r], X.x, Q.y));
+            const float t1 = __builtin_fmaf(m2y[r], Y.y, __builtin_fmaf(m2x[r], X.y, Q.z));
+            const float t2 = __builtin_fmaf(m2y[r], Y.z, __builtin_fmaf(m2x[r], X.z, Q.w));
+            const float t3 = __builtin_fmaf(m2y[r], Y.w, __builtin_fmaf(m2x[r], X.w, Q.x));
+            m[r] = fminf(fminf(m[r], t0), t1);
+            m[r] = fminf(fminf(m[r], t2), t3);
+        }
+    }
+}
+
+// scan_edges with whole blocks skipped.  thr[r] bounds what corner r still
+// needs: a block whose box_lb exceeds thr[r] for every corner of the wave
+// (a wave-uniform decision, by ballot) is not folded, and a chunk none of
+// whose blocks is needed is neither loaded nor staged.  The caller sets
+// thr = D(corner, q) + 2 band for a point q it knows (or +inf): the block of
+// q is then always folded, so the chunk minima kept here include the
+// overall minimum of T, and every skipped point has T above that minimum
+// plus the band (T and D agree within a quarter band), so no skipped chunk
+// could have been a candidate.  -inf marks a corner that needs nothing.
+template <int R>
+__device__ __forceinline__ void scan_edges_pruned(const float *__restrict__ stream, const float4 *__restrict__ cbox,
+                                                  const float4 *__restrict__ box, int c0, int c1, float4 *stage,
+                                                  const float (&cx)[R], const float (&cy)[R], const float (&thr)[R],
+                                                  float (&b1)[R], float (&b2)[R], float (&b3)[R], int (&i1)[R],
+                                                  int (&i2)[R])
+{
+    constexpr int kC4 = kStageBytes / 16;             // float4 per chunk
+    static_assert(kC4 > 64 && kC4 <= 128, "two 16-byte pieces per lane");
+    static_assert(kChunk == 4 * 32, "four blocks of 32 points per chunk");
+    const int lane = threadIdx.x & 63;
+    const bool second = lane < kC4 - 64;
+    const float4 *src = (const float4 *)stream + lane;
+    float m2x[R], m2y[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        m2x[r] = -2.0f * cx[r];
+        m2y[r] = -2.0f * cy[r];
+    }
+    // the blocks of chunk c some corner of the wave needs (bit sb), 0 if none
+    auto need = [&](int c) -> uint32_t {
+        bool any = false;
+        const float4 cb = cbox[c];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            any = any || box_lb(cb, cx[r], cy[r]) <= thr[r];
+        if (__ballot(any) == 0)
+            return 0u;
+        uint32_t msk = 0;
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) {
+            const float4 bb = box[4 * c + sb];
+            bool a = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                a = a || box_lb(bb, cx[r], cy[r]) <= thr[r];
+            if (__ballot(a) != 0)
+                msk |= 1u << sb;
+        }
+        return msk;
+    };
+    int c = c0;
+    uint32_t msk = 0;
+    for (; c < c1; ++c)
+        if ((msk = need(c)) != 0)
+            break;
+    if (c >= c1)
+        return;
+    float4 va = src[(long)kC4 * c], vb = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (second)
+        vb = src[(long)kC4 * c + 64];
+    for (;;) {
+        stage[lane] = va;
+        if (second)
+            stage[64 + lane] = vb;
+        // the next needed chunk is fetched while this one is folded
+        int cn = c + 1;
+        uint32_t mn = 0;
+        for (; cn < c1; ++cn)
+            if ((mn = need(cn)) != 0)
+                break;
+        if (cn < c1) {
+            va = src[(long)kC4 * cn];
+            if (second)
+                vb = src[(long)kC4 * cn + 64];
+        }
+        float m[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            m[r] = __builtin_inff();
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+            if (msk & (1u << sb))
+                fold_block<R>(stage, sb, m2x, m2y, m);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool lt1 = m[r] < b1[r], lt2 = m[r] < b2[r];
+            b3[r] = __builtin_amdgcn_fmed3f(b2[r], b3[r], m[r]);
+            b2[r] = __builtin_amdgcn_fmed3f(b1[r], b2[r], m[r]);
+            b1[r] = lt1 ? m[r] : b1[r];
+            const int j2 = lt2 ? c : i2[r];
+            i2[r] = lt1 ? i1[r] : j2;
+            i1[r] = lt1 ? c : i1[r];
+        }
+        if (cn >= c1)
+            break;
+        c = cn;
+        msk = mn;
+    }
+}
+
 // Exact rescan of part rl (of kRescanLanes) of chunk `c` for one corner:
 // the lowest index of the minimum of D over the part's real points (index <
 // E), points c * kChunk + rl * kRescanPart + k in ascending k, folded into

@@ -30,12 +30,19 @@ __host__ __device__ inline long edge_base(int rg_off_s, int s)
 // groups of four, see qq_slot in wm_device.h; padding points have
 // x = y = 0 and qq = +inf); `dir` and `idx` (scenario-local original index)
 // are indexed by point.  `count` = edges per scenario, `qqmax` = their max qq.
+// `box` holds, per 32 stream points (a block), the box (xmin, xmax, ymin,
+// ymax) of its edge points, and `cbox` the same per chunk; blocks and chunks
+// of a scenario start at box[base / 32] and cbox[base / 128].  A box without
+// points is (+inf, -inf, +inf, -inf).
+constexpr int kBoxPts = 32;
 struct Edges {
     float *stream;
     float2 *dir;
     int32_t *idx;
     int32_t *count;
     float *qqmax;
+    float4 *box;
+    float4 *cbox;
 };
 
 struct StepArgs {
@@ -125,7 +132,7 @@ constexpr int kRecFields = 16;
 
 // Workspace sections (byte offsets, each 256-aligned).
 struct WsLayout {
-    size_t ecount, stream, edir, eidx, qqmax, uoff, units, lossp, counter, seg, idmP, idmA, total;
+    size_t ecount, stream, edir, eidx, qqmax, ebox, ecbox, uoff, units, lossp, counter, seg, idmP, idmA, total;
 };
 
 inline WsLayout ws_layout(int S, int n, int P, int T, int K)
@@ -139,6 +146,8 @@ inline WsLayout ws_layout(int S, int n, int P, int T, int K)
     L.edir = take(sizeof(float) * 2 * cap);
     L.eidx = take(sizeof(int32_t) * cap);
     L.qqmax = take(sizeof(float) * (size_t)S);
+    L.ebox = take(sizeof(float) * 4 * (cap / kBoxPts + 1));
+    L.ecbox = take(sizeof(float) * 4 * (cap / kEdgeChunk + 1));
     L.uoff = take(sizeof(int32_t) * ((size_t)S + 1));
     L.units = take(sizeof(int32_t) * 2 * ((size_t)n + 1));
     L.lossp = take(sizeof(float) * ((size_t)n + 1));
@@ -153,13 +162,15 @@ inline WsLayout ws_layout(int S, int n, int P, int T, int K)
 inline Edges ws_edges(unsigned char *ws, const WsLayout &L)
 {
     return Edges{(float *)(ws + L.stream), (float2 *)(ws + L.edir), (int32_t *)(ws + L.eidx),
-                 (int32_t *)(ws + L.ecount), (float *)(ws + L.qqmax)};
+                 (int32_t *)(ws + L.ecount), (float *)(ws + L.qqmax), (float4 *)(ws + L.ebox),
+                 (float4 *)(ws + L.ecbox)};
 }
 
 // Launchers (wm_kernels.hip).  They only enqueue; errors surface through
 // hipGetLastError in the caller.
 void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned char *ws, const WsLayout &L,
                           hipStream_t st);
+void launch_edge_boxes(const wm_batch &b, unsigned char *ws, const WsLayout &L, hipStream_t st);
 void launch_build_units(const wm_batch &b, int U, const int32_t *ecount, unsigned char *ws, const WsLayout &L,
                         hipStream_t st);
 void launch_dynamics(const wm_batch &b, const StepArgs &a, hipStream_t st);

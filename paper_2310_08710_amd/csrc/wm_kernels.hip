@@ -94,6 +94,46 @@ __global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Boxes of the compacted road edges: per block of 32 stream points and per
+// chunk, the box of its edge points (padding excluded).  One work-group per
+// scenario, one thread per chunk.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_edge_boxes(const int32_t *__restrict__ rg_off, Edges E)
+{
+    const int s = blockIdx.x;
+    const long base = edge_base(rg_off[s], s);
+    const int cnt = E.count[s];
+    const int nch = (cnt + kChunk - 1) / kChunk;
+    const float *stream = E.stream + 3 * base;
+    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        const float4 *X = (const float4 *)(stream + (long)kChunkFloats * c);
+        const float4 *Y = (const float4 *)(stream + (long)kChunkFloats * c + kChunk);
+        float4 cb = make_float4(__builtin_inff(), -__builtin_inff(), __builtin_inff(), -__builtin_inff());
+        for (int sb = 0; sb < kChunk / kBoxPts; ++sb) {
+            float4 bb = make_float4(__builtin_inff(), -__builtin_inff(), __builtin_inff(), -__builtin_inff());
+#pragma unroll
+            for (int q = 0; q < kBoxPts / 4; ++q) {
+                const int g4 = sb * (kBoxPts / 4) + q;
+                const float4 xs = X[g4], ys = Y[g4];
+                const float xv[4] = {xs.x, xs.y, xs.z, xs.w}, yv[4] = {ys.x, ys.y, ys.z, ys.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (kChunk * c + 4 * g4 + k < cnt) {
+                        bb.x = fminf(bb.x, xv[k]);
+                        bb.y = fmaxf(bb.y, xv[k]);
+                        bb.z = fminf(bb.z, yv[k]);
+                        bb.w = fmaxf(bb.w, yv[k]);
+                    }
+                }
+            }
+            E.box[base / kBoxPts + (kChunk / kBoxPts) * c + sb] = bb;
+            cb = make_float4(fminf(cb.x, bb.x), fmaxf(cb.y, bb.y), fminf(cb.z, bb.z), fmaxf(cb.w, bb.w));
+        }
+        E.cbox[base / kChunk + c] = cb;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Work units of the persistent rollout: scenario s is cut into
 // ceil(N_s / U) slices of U objects.  Unit ids are scenario-major
 // (uoff[s] + slice); the queue holds them in descending cost order, a
@@ -519,6 +559,261 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
         }
         __syncthreads();
     }
+}
+
+// The fused rollout's off-road step for slice objects i0 .. i0+Ns-1 (the
+// result of offroad_unit, with the scan pruned).  The unit's objects are
+// taken in `order` (spatial order, see spatial_order) in groups of 16 R:
+// W = blockDim / 64 waves form NG = min(W, Ns_max / 16) groups; the
+// W / NG waves of a group split its chunks; a lane holds corner (lane & 3) of
+// the group's objects (lane >> 2) + 16 r, r < R.  prevj[slot] (slot = 4 il +
+// corner) is the corner's nearest stream point of the previous step (-1:
+// none), whose distance bounds what the scan must look at (scan_edges_pruned);
+// this step's nearest point replaces it.
+template <int R>
+__device__ void offroad_group_scan(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
+                                   const float4 *__restrict__ cbox, const float4 *__restrict__ box, int E,
+                                   float qqmax, int NG, int splits, const ScanLds &C, int SL, const int *order,
+                                   const int *prevj)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int sg = w % NG, g = w / NG;
+    const int nch = (E + kChunk - 1) / kChunk;
+    const int cps = (nch + splits - 1) / splits;
+    const int c0 = min(nch, g * cps), c1 = min(nch, c0 + cps);
+    float cx[R], cy[R], thr[R], b1[R], b2[R], b3[R];
+    int i1[R], i2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int rank = 16 * R * sg + (lane >> 2) + 16 * r;
+        const int il = rank < Ns ? order[rank] : -1;
+        const int o = i0 + max(il, 0);
+        box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], lane & 3, cx[r], cy[r]);
+        thr[r] = -__builtin_inff();   // needs nothing
+        if (il >= 0 && L.valid[o]) {
+            const int j = prevj[4 * il + (lane & 3)];
+            thr[r] = __builtin_inff();
+            if (j >= 0) {
+                const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
+                thr[r] = edge_d2(ch[0], ch[kChunk], cx[r], cy[r]) + 2.0f * candidate_band(qqmax, cx[r], cy[r]);
+            }
+        }
+        b1[r] = b2[r] = b3[r] = __builtin_inff();
+        i1[r] = i2[r] = -1;
+    }
+    float4 *stage = C.stage + (long)w * (kStageBytes / 16);
+    if (c0 < c1)
+        scan_edges_pruned<R>(stream, cbox, box, c0, c1, stage, cx, cy, thr, b1, b2, b3, i1, i2);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int rank = 16 * R * sg + (lane >> 2) + 16 * r;
+        if (rank < Ns) {
+            const int at = g * SL + 4 * order[rank] + (lane & 3);
+            C.b1[at] = b1[r];
+            C.b2[at] = b2[r];
+            C.b3[at] = b3[r];
+            C.i1[at] = i1[r];
+            C.i2[at] = i2[r];
+        }
+    }
+}
+
+__device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, const float *__restrict__ stream,
+                                    const float2 *__restrict__ edir, const int32_t *__restrict__ eidx,
+                                    const float4 *__restrict__ cbox, const float4 *__restrict__ box, int E,
+                                    float qqmax, ScanLds C, float *sk, int *nidx, const int *order, int *prevj)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int W = blockDim.x >> 6;
+    const int NG = min(W, U / 16), splits = W / NG, R = U / (16 * NG);
+    const int SL = 4 * U;
+    const int nslots = 4 * Ns;
+    if (tid == 0)
+        *C.nfull = 0;
+    if (R == 1)
+        offroad_group_scan<1>(L, i0, Ns, stream, cbox, box, E, qqmax, NG, splits, C, SL, order, prevj);
+    else if (R == 2)
+        offroad_group_scan<2>(L, i0, Ns, stream, cbox, box, E, qqmax, NG, splits, C, SL, order, prevj);
+    else
+        offroad_group_scan<4>(L, i0, Ns, stream, cbox, box, E, qqmax, NG, splits, C, SL, order, prevj);
+    __syncthreads();
+    for (int slot = tid; slot < nslots; slot += blockDim.x) {
+        // best chunk over the splits (ascending splits hold ascending chunks)
+        float b = __builtin_inff();
+        int bc = -1;
+        for (int h = 0; h < splits; ++h) {
+            const float v = C.b1[h * SL + slot];
+            if (v < b) {
+                b = v;
+                bc = C.i1[h * SL + slot];
+            }
+        }
+        const int o = i0 + (slot >> 2);
+        int lo = -1, hi = -1;   // candidate chunks; lo: -1 none, -2 the exact scan of every point
+        if (bc >= 0 && L.valid[o]) {
+            float x, y;
+            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+            const float lim = b + candidate_band(qqmax, x, y);
+            int other = -1;        // a second candidate chunk
+            bool full = false;     // three or more candidates: exact scan of every chunk
+            for (int h = 0; h < splits; ++h) {
+                const int at = h * SL + slot;
+                if (C.b3[at] <= lim)
+                    full = true;
+                const int cand[2] = {C.i1[at], C.i2[at]};
+                const float val[2] = {C.b1[at], C.b2[at]};
+                for (int q = 0; q < 2; ++q) {
+                    if (val[q] <= lim && cand[q] != bc && cand[q] != other) {
+                        if (other < 0)
+                            other = cand[q];
+                        else
+                            full = true;
+                    }
+                }
+            }
+            if (full) {
+                C.full[atomicAdd(C.nfull, 1)] = slot;
+                lo = -2;
+            } else {
+                lo = other >= 0 ? min(bc, other) : bc;
+                hi = other >= 0 ? max(bc, other) : -1;
+            }
+        }
+        nidx[slot] = lo;
+        sk[slot] = __int_as_float(hi);
+    }
+    __syncthreads();
+    for (int u0 = 0; u0 < nslots * kRescanLanes; u0 += blockDim.x) {   // block-uniform trip count
+        const int u = u0 + tid, slot = u / kRescanLanes, rl = u % kRescanLanes;
+        const bool act = slot < nslots;
+        const int lo = act ? nidx[slot] : -1, hi = act ? __float_as_int(sk[slot]) : -1;
+        float best = __builtin_inff(), x = 0.f, y = 0.f;
+        int bj = 0x7fffffff;
+        if (lo >= 0) {
+            const int o = i0 + (slot >> 2);
+            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+            rescan_part(stream, lo, rl, E, x, y, best, bj);
+            if (hi >= 0)
+                rescan_part(stream, hi, rl, E, x, y, best, bj);
+        }
+        for (int off = kRescanLanes / 2; off > 0; off >>= 1) {
+            const float ob = __shfl_xor(best, off);
+            const int oj = __shfl_xor(bj, off);
+            if (ob < best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if (act && rl == 0) {
+            float s_val = kNoValue;
+            int near = -1, pj = -1;
+            if (lo >= 0 && bj != 0x7fffffff) {
+                const float *ch = stream + kChunkFloats * (bj / kChunk) + (bj % kChunk);
+                const float qx = ch[0], qy = ch[kChunk];
+                const float2 d = edir[bj];
+                s_val = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
+                near = eidx[bj];
+                pj = bj;
+            }
+            if (lo != -2)
+                prevj[slot] = pj;
+            sk[slot] = s_val;
+            nidx[slot] = near;
+        }
+    }
+    __syncthreads();
+    const int nf = *C.nfull;
+    const int nthr = blockDim.x, nw = nthr >> 6, w = tid >> 6;
+    for (int f = 0; f < nf; ++f) {
+        const int slot = C.full[f];
+        const int o = i0 + (slot >> 2);
+        float x, y;
+        box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+        float best = __builtin_inff();
+        int bj = 0x7fffffff;
+        for (int j0 = tid; j0 < E; j0 += 8 * nthr) {
+            float px[8], py[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = min(j0 + u * nthr, E - 1);
+                const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
+                px[u] = ch[0];
+                py[u] = ch[kChunk];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = j0 + u * nthr;
+                const float d = edge_d2(px[u], py[u], x, y);
+                if (j < E && d < best) {
+                    best = d;
+                    bj = j;
+                }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const float ob = __shfl_xor(best, off);
+            const int oj = __shfl_xor(bj, off);
+            if (ob < best || (ob == best && oj < bj)) {
+                best = ob;
+                bj = oj;
+            }
+        }
+        if (lane == 0) {
+            C.b1[w] = best;
+            C.i1[w] = bj;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            float b = __builtin_inff();
+            int j = 0x7fffffff;
+            for (int v = 0; v < nw; ++v)
+                if (C.b1[v] < b || (C.b1[v] == b && C.i1[v] < j)) {
+                    b = C.b1[v];
+                    j = C.i1[v];
+                }
+            if (j != 0x7fffffff) {
+                const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
+                const float qx = ch[0], qy = ch[kChunk];
+                const float2 d = edir[j];
+                sk[slot] = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
+                nidx[slot] = eidx[j];
+            }
+            prevj[slot] = j != 0x7fffffff ? j : -1;
+        }
+        __syncthreads();
+    }
+}
+
+// Spatial order of slice objects i0 .. i0+Ns-1: ascending by the Morton code
+// of their 8 m cell (invalid objects last), ties by index, into order[].
+// Neighbouring objects then share the waves of the pruned scan.  Two
+// barriers.
+__device__ __forceinline__ void spatial_order(const ObjLds &L, int i0, int Ns, uint32_t *key, int *order)
+{
+    for (int il = threadIdx.x; il < Ns; il += blockDim.x) {
+        const int o = i0 + il;
+        uint32_t k = 0xffffffffu;
+        if (L.valid[o]) {
+            const uint32_t gx = (uint32_t)min(max((int)floorf(L.x[o] * 0.125f) + 2048, 0), 4095);
+            const uint32_t gy = (uint32_t)min(max((int)floorf(L.y[o] * 0.125f) + 2048, 0), 4095);
+            k = 0;
+            for (int b = 0; b < 12; ++b)
+                k |= ((gx >> b) & 1u) << (2 * b) | ((gy >> b) & 1u) << (2 * b + 1);
+        }
+        key[il] = k;
+    }
+    __syncthreads();
+    for (int il = threadIdx.x; il < Ns; il += blockDim.x) {
+        const uint32_t k = key[il];
+        int rank = 0;
+        for (int j = 0; j < Ns; ++j) {
+            const uint32_t kj = key[j];
+            rank += (kj < k || (kj == k && j < il)) ? 1 : 0;
+        }
+        order[rank] = il;
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ void load_object(ObjLds &L, int i, const wm_state &st, long g)
@@ -964,6 +1259,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     uint8_t *agent = (uint8_t *)(lk + A.maxN);
     float *pc = (float *)(agent + align_up((size_t)A.maxN, 16));   // IDM: pose at sig (x, y)
     uint32_t *mask = (uint32_t *)(pc + 2 * A.maxN);                   // IDM: candidate bit masks
+    // the pruned off-road scan: spatial keys and order of the slice's
+    // objects, each corner's nearest stream point of the previous step
+    uint32_t *okey = (uint32_t *)align_up((size_t)(mask + (A.maxN <= kIdmMaskMaxN ? A.maxN * ((A.maxN + 31) / 32) : 0)), 16);
+    int *order = (int *)(okey + U);
+    int *prevj = order + U;
     __shared__ int s_unit;
     const int tid = threadIdx.x;
     const long n = A.n;
@@ -997,6 +1297,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (A.has_ckpt)
             for (int il = tid; il < Ns; il += nthr)
                 store_object(L, i0 + il, A.ckpt, o0 + i0 + il);
+        for (int k = tid; k < 4 * U; k += nthr)
+            prevj[k] = -1;
         __syncthreads();
         float my_loss = 0.f;
         for (int t = 1; t <= A.T; ++t) {
@@ -1043,8 +1345,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
             overlap_partial(L, N, i0, Ns, U, P, red, A.want_loss ? &my_loss : nullptr, nullptr, nullptr);
             if (A.has_rg) {
-                offroad_unit(L, i0, Ns, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb, E, qqmax, A.G, A.CW, C, sk,
-                             nidx);
+                spatial_order(L, i0, Ns, okey, order);
+                offroad_unit_pruned(L, i0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb,
+                                    A.E.cbox + eb / kChunk, A.E.box + eb / kBoxPts, E, qqmax, C, sk, nidx, order,
+                                    prevj);
             } else {
                 __syncthreads();
             }
@@ -1117,6 +1421,11 @@ void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned ch
     hipLaunchKernelGGL(k_compact_edges<256>, dim3(b.num_scenarios), dim3(256), 0, st, b.rg_off, rg, ws_edges(ws, L));
 }
 
+void launch_edge_boxes(const wm_batch &b, unsigned char *ws, const WsLayout &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_edge_boxes, dim3(b.num_scenarios), dim3(256), 0, st, b.rg_off, ws_edges(ws, L));
+}
+
 void launch_build_units(const wm_batch &b, int U, const int32_t *ecount, unsigned char *ws, const WsLayout &L,
                         hipStream_t st)
 {
@@ -1167,7 +1476,8 @@ size_t rollout_lds_bytes(int maxN, int G, int CW)
     const int nthr = 64 * CW * G;
     const size_t idm = (size_t)maxN * 12 + align_up((size_t)maxN, 16) + (size_t)maxN * 8 +
                        (maxN <= kIdmMaskMaxN ? (size_t)maxN * ((maxN + 31) / 32) * 4 : 0);
-    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up(idm, 16);
+    const size_t prune = (size_t)64 * CW * 24 + 16;   // keys, order, previous nearest points
+    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up(idm, 16) + prune;
 }
 
 void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float4 *path, uint8_t *agent,
