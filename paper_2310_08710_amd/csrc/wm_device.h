@@ -392,129 +392,243 @@ __device__ __forceinline__ void scan_edges(const float *__restrict__ stream, int
 __device__ __forceinline__ float box_lb(const float4 bb, float cx, float cy)
 {
     const float lx = bb.x - cx, hx = bb.y - cx, ly = bb.z - cy, hy = bb.w - cy;
-    const float dx = lx > 0.f ? lx : (hx < 0.f ? -hx : 0.f);
-    const float dy = ly > 0.f ? ly : (hy < 0.f ? -hy : 0.f);
+    // lx > 0 and hx < 0 exclude each other (xmin <= xmax; an empty box has
+    // lx = +inf), so the larger of lx, -hx and 0 is the distance along x
+    const float dx = fmaxf(fmaxf(lx, -hx), 0.f);
+    const float dy = fmaxf(fmaxf(ly, -hy), 0.f);
     return __builtin_fmaf(dy, dy, dx * dx);
 }
 
-// Minimum of T over the 32 points of block sb (0..3) of a chunk staged in
-// LDS, folded into m: fold_chunk restricted to that block.
-template <int R>
-__device__ __forceinline__ void fold_block(const float4 *stage, int sb, const float (&m2x)[R],
-                                           const float (&m2y)[R], float (&m)[R])
+// The pruned scan (scan_group_pruned) stages up to kPruneBatch blocks at a
+// time per wave; a staged block is its 32 points' x, y and qq, 8 float4 each
+// (kBlockF4).  Per wave it also lists the needed blocks (kPruneList 16-bit
+// entries).
+constexpr int kPruneBatch = 8;
+constexpr int kBlockF4 = 24;
+constexpr int kPruneStageBytes = kPruneBatch * kBlockF4 * 16;
+constexpr int kPruneList = 512;
+constexpr int kPruneWaveBytes = kPruneStageBytes + kPruneList * 2;
+
+// Minimum over the lanes of a group of CL consecutive lanes (CL = 4, 8 or
+// 16), in every lane of the group (quad swaps, then half-row and row
+// mirrors).
+template <int Ctrl>
+__device__ __forceinline__ float dpp_min(float v)
 {
-#pragma unroll 4
-    for (int j4 = 8 * sb; j4 < 8 * sb + 8; ++j4) {
-        const float4 X = stage[j4], Y = stage[kChunk / 4 + j4], Q = stage[kChunk / 2 + j4];
+    return fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false)));
+}
+
+template <int CL>
+__device__ __forceinline__ float lanes_min(float v)
+{
+    static_assert(CL == 4 || CL == 8 || CL == 16, "lane groups of 4, 8 or 16");
+    v = dpp_min<0xB1>(v);       // quad_perm [1, 0, 3, 2]
+    v = dpp_min<0x4E>(v);       // quad_perm [2, 3, 0, 1]
+    if constexpr (CL >= 8)
+        v = dpp_min<0x141>(v);  // row_half_mirror
+    if constexpr (CL >= 16)
+        v = dpp_min<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Sum over the lanes of a group of 8 consecutive lanes, in every lane of it.
+template <int Ctrl>
+__device__ __forceinline__ int dpp_add(int v)
+{
+    return v + __builtin_amdgcn_update_dpp(0, v, Ctrl, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ int lanes_sum8(int v)
+{
+    v = dpp_add<0xB1>(v);
+    v = dpp_add<0x4E>(v);
+    return dpp_add<0x141>(v);
+}
+
+// Minimum of T over this lane's PL points (part `part`) of a staged block,
+// folded into m.
+template <int PL>
+__device__ __forceinline__ void fold_part(const float4 *st, int part, float m2x, float m2y, float &m)
+{
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float t0 = __builtin_fmaf(m2y[r], Y.x, __builtin_fmaf(m2x[r], X.x, Q.y));
-            const float t1 = __builtin_fmaf(m2y[r], Y.y, __builtin_fmaf(m2x[r], X.y, Q.z));
-            const float t2 = __builtin_fmaf(m2y[r], Y.z, __builtin_fmaf(m2x[r], X.z, Q.w));
-            const float t3 = __builtin_fmaf(m2y[r], Y.w, __builtin_fmaf(m2x[r], X.w, Q.x));
-            m[r] = fminf(fminf(m[r], t0), t1);
-            m[r] = fminf(fminf(m[r], t2), t3);
-        }
+    for (int q = 0; q < PL / 4; ++q) {
+        const int j4 = part * (PL / 4) + q;
+        const float4 X = st[j4], Y = st[8 + j4], Q = st[16 + j4];
+        // Q holds the group's qq rotated by one (qq_slot)
+        const float t0 = __builtin_fmaf(m2y, Y.x, __builtin_fmaf(m2x, X.x, Q.y));
+        const float t1 = __builtin_fmaf(m2y, Y.y, __builtin_fmaf(m2x, X.y, Q.z));
+        const float t2 = __builtin_fmaf(m2y, Y.z, __builtin_fmaf(m2x, X.z, Q.w));
+        const float t3 = __builtin_fmaf(m2y, Y.w, __builtin_fmaf(m2x, X.w, Q.x));
+        m = fminf(fminf(m, t0), t1);
+        m = fminf(fminf(m, t2), t3);
     }
 }
 
-// scan_edges with whole blocks skipped.  thr[r] bounds what corner r still
-// needs: a block whose box_lb exceeds thr[r] for every corner of the wave
-// (a wave-uniform decision, by ballot) is not folded, and a chunk none of
-// whose blocks is needed is neither loaded nor staged.  The caller sets
-// thr = D(corner, q) + 2 band for a point q it knows (or +inf): the block of
-// q is then always folded, so the chunk minima kept here include the
-// overall minimum of T, and every skipped point has T above that minimum
-// plus the band (T and D agree within a quarter band), so no skipped chunk
-// could have been a candidate.  -inf marks a corner that needs nothing.
-template <int R>
-__device__ __forceinline__ void scan_edges_pruned(const float *__restrict__ stream, const float4 *__restrict__ cbox,
-                                                  const float4 *__restrict__ box, int c0, int c1, float4 *stage,
-                                                  const float (&cx)[R], const float (&cy)[R], const float (&thr)[R],
-                                                  float (&b1)[R], float (&b2)[R], float (&b3)[R], int (&i1)[R],
-                                                  int (&i2)[R])
+// The block minima of the road-edge scan for the 4 GO corners of a group of
+// GO objects, with whole blocks of 32 points skipped.  Corner k is held by
+// the CL = 16 / GO lanes k CL .. k CL + CL - 1 (each with the corner's cx,
+// cy and thr); a lane folds PL = 32 / CL points of each block, and the
+// lanes' minima are combined per block.  On return every lane of a corner
+// holds its (b1, b2, b3, i1, i2): the three smallest block minima of T over
+// the folded blocks and the blocks (index 4 chunk + block) of the first two,
+// as scan_edges keeps them per chunk.
+//
+// thr bounds what the corner still needs: a block whose box_lb exceeds thr
+// for every corner of the group is neither loaded nor folded.  The caller
+// sets thr = D(corner, q) + 2 band for a point q it knows (or +inf): the
+// block of q is then always folded, so the chunk minima kept here include
+// the overall minimum of T, and every skipped point has T above that minimum
+// plus the band (T and D agree within a quarter band), so no chunk with
+// skipped points only could have been a candidate.  -inf marks a corner that
+// needs nothing.
+//
+// The tests run with a box per lane: per pass of 64 chunks, lane j tests
+// chunk box j against every corner (broadcast from its lanes), then lane l
+// tests block l & 3 of the (l >> 2)-th needed chunk, 16 needed chunks at a
+// time; the needed blocks are listed in ascending order and fetched
+// kPruneBatch at a time, two per 16-byte load (lanes 0..47), the next batch
+// in flight while one is folded from `stage`.  cbox and box may point to
+// global memory or to a copy in LDS.
+template <int GO>
+__device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stream, const float4 *cbox,
+                                                  const float4 *box, int nch, float4 *stage, uint16_t *list,
+                                                  float cx, float cy, float thr, float &b1, float &b2, float &b3,
+                                                  int &i1, int &i2)
 {
-    constexpr int kC4 = kStageBytes / 16;             // float4 per chunk
-    static_assert(kC4 > 64 && kC4 <= 128, "two 16-byte pieces per lane");
-    static_assert(kChunk == 4 * 32, "four blocks of 32 points per chunk");
-    const int lane = threadIdx.x & 63;
-    const bool second = lane < kC4 - 64;
-    const float4 *src = (const float4 *)stream + lane;
-    float m2x[R], m2y[R];
+    constexpr int NC = 4 * GO, CL = 64 / NC, PL = 32 / CL;
+    constexpr int kChunkF4 = kStageBytes / 16;   // float4 per chunk in the stream
+    static_assert(kChunk == 4 * 32 && kChunkF4 == 3 * 32, "four blocks of 32 points per chunk");
+    static_assert(PL % 4 == 0, "whole groups of four points per lane");
+    static_assert(kPruneBatch % 2 == 0 && 2 * kBlockF4 <= 64, "two blocks per load");
+    const int lane = threadIdx.x & 63, part = lane % CL;
+    const float4 *src = (const float4 *)stream;
+    const float4 empty = make_float4(__builtin_inff(), -__builtin_inff(), __builtin_inff(), -__builtin_inff());
+    const float m2x = -2.0f * cx, m2y = -2.0f * cy;
+    // is this lane's box needed by some corner of the group
+    auto any_corner = [&](const float4 b) -> bool {
+        bool a = false;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        m2x[r] = -2.0f * cx[r];
-        m2y[r] = -2.0f * cy[r];
-    }
-    // the blocks of chunk c some corner of the wave needs (bit sb), 0 if none
-    auto need = [&](int c) -> uint32_t {
-        bool any = false;
-        const float4 cb = cbox[c];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            any = any || box_lb(cb, cx[r], cy[r]) <= thr[r];
-        if (__ballot(any) == 0)
-            return 0u;
-        uint32_t msk = 0;
-#pragma unroll
-        for (int sb = 0; sb < 4; ++sb) {
-            const float4 bb = box[4 * c + sb];
-            bool a = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                a = a || box_lb(bb, cx[r], cy[r]) <= thr[r];
-            if (__ballot(a) != 0)
-                msk |= 1u << sb;
+        for (int k = 0; k < NC; ++k) {
+            const float kx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cx), k * CL));
+            const float ky = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cy), k * CL));
+            const float kt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(thr), k * CL));
+            a |= box_lb(b, kx, ky) <= kt;
         }
-        return msk;
+        return a;
     };
-    int c = c0;
-    uint32_t msk = 0;
-    for (; c < c1; ++c)
-        if ((msk = need(c)) != 0)
-            break;
-    if (c >= c1)
-        return;
-    float4 va = src[(long)kC4 * c], vb = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (second)
-        vb = src[(long)kC4 * c + 64];
-    for (;;) {
-        stage[lane] = va;
-        if (second)
-            stage[64 + lane] = vb;
-        // the next needed chunk is fetched while this one is folded
-        int cn = c + 1;
-        uint32_t mn = 0;
-        for (; cn < c1; ++cn)
-            if ((mn = need(cn)) != 0)
-                break;
-        if (cn < c1) {
-            va = src[(long)kC4 * cn];
-            if (second)
-                vb = src[(long)kC4 * cn + 64];
+    float m = __builtin_inff();
+    // m (this lane's part) becomes the minimum of block blk
+    auto flush = [&](int cur) {
+        const float mm = lanes_min<CL>(m);
+        const bool lt1 = mm < b1, lt2 = mm < b2;
+        b3 = __builtin_amdgcn_fmed3f(b2, b3, mm);
+        b2 = __builtin_amdgcn_fmed3f(b1, b2, mm);
+        b1 = lt1 ? mm : b1;
+        const int j2 = lt2 ? cur : i2;
+        i2 = lt1 ? i1 : j2;
+        i1 = lt1 ? cur : i1;
+        m = __builtin_inff();
+    };
+    // this lane's piece of a block: column (x, y, qq) piece / 8, float4 piece % 8
+    const int half = lane / kBlockF4, piece = lane % kBlockF4;
+    const int poff = (piece / 8) * (kChunk / 4) + piece % 8;
+    const bool loader = half < 2;
+    int seg = 0;    // list entries are 4 (chunk - seg) + block
+    int nl = 0;
+    float4 v[kPruneBatch / 2];
+    // slot s of a batch from b0: blocks b0 + 2 s (lanes 0..23) and b0 + 2 s + 1 (lanes 24..47)
+    auto fetch = [&](int b0, int nb) {
+#pragma unroll
+        for (int s = 0; s < kPruneBatch / 2; ++s) {
+            const int i = 2 * s + half;
+            if (loader && i < nb) {
+                const int e = list[b0 + i];
+                v[s] = src[(long)kChunkF4 * (seg + (e >> 2)) + (e & 3) * 8 + poff];
+            }
         }
-        float m[R];
+    };
+    auto fold_list = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        if (nl == 0)
+            return;
+        fetch(0, min(kPruneBatch, nl));
+        for (int b0 = 0; b0 < nl; b0 += kPruneBatch) {
+            const int nb = min(kPruneBatch, nl - b0);
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            m[r] = __builtin_inff();
-#pragma unroll
-        for (int sb = 0; sb < 4; ++sb)
-            if (msk & (1u << sb))
-                fold_block<R>(stage, sb, m2x, m2y, m);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const bool lt1 = m[r] < b1[r], lt2 = m[r] < b2[r];
-            b3[r] = __builtin_amdgcn_fmed3f(b2[r], b3[r], m[r]);
-            b2[r] = __builtin_amdgcn_fmed3f(b1[r], b2[r], m[r]);
-            b1[r] = lt1 ? m[r] : b1[r];
-            const int j2 = lt2 ? c : i2[r];
-            i2[r] = lt1 ? i1[r] : j2;
-            i1[r] = lt1 ? c : i1[r];
+            for (int s = 0; s < kPruneBatch / 2; ++s)
+                if (loader && 2 * s < nb)
+                    stage[2 * kBlockF4 * s + lane] = v[s];
+            if (b0 + kPruneBatch < nl)
+                fetch(b0 + kPruneBatch, min(kPruneBatch, nl - b0 - kPruneBatch));
+            __builtin_amdgcn_wave_barrier();
+            const int ent = lane < nb ? (int)list[b0 + lane] : 0;   // the batch's entries, one per lane
+            for (int i = 0; i < nb; ++i) {
+                fold_part<PL>(stage + kBlockF4 * i, part, m2x, m2y, m);
+                flush(4 * seg + __builtin_amdgcn_readlane(ent, i));
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        if (cn >= c1)
-            break;
-        c = cn;
-        msk = mn;
+        nl = 0;
+    };
+    for (int base = 0; base < nch; base += 64) {
+        // room for a whole pass (256 entries) within 16-bit entries
+        if (nl > kPruneList - 256 || base + 64 - seg > 16384)
+            fold_list();
+        if (nl == 0)
+            seg = base;
+        const int cnt = min(64, nch - base);
+        const float4 cb = lane < cnt ? cbox[base + lane] : empty;
+        // bit j: chunk base + j has a needed point (lanes past the range hold
+        // an empty box, which a corner with thr = +inf would pass)
+        uint64_t cm = __ballot(lane < cnt && any_corner(cb));
+        while (cm != 0) {
+            // lane l: block (l & 3) of the (l >> 2)-th needed chunk of this batch
+            int myc = -1;
+            for (int nb = 0; nb < 16 && cm != 0; ++nb) {
+                const int j = __builtin_ctzll(cm);
+                cm &= cm - 1;
+                if ((lane >> 2) == nb)
+                    myc = base + j;
+            }
+            const float4 bb = myc >= 0 ? box[4 * myc + (lane & 3)] : empty;
+            const uint64_t bm = __ballot(myc >= 0 && any_corner(bb));   // bit l: lane l's block is needed
+            const int below =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0));
+            if ((bm >> lane) & 1ull)
+                list[nl + below] = (uint16_t)(4 * (myc - seg) + (lane & 3));
+            nl += __popcll(bm);
+        }
+    }
+    fold_list();
+}
+
+// Exact rescan of part rl (of kBlockRescanLanes) of block `blk` (points
+// 32 blk ..) for one corner, as rescan_part does for a chunk: the lowest
+// index of the minimum of D over the part's real points (index < E), folded
+// into (best, bidx) with strict <, the points in ascending order.
+constexpr int kBlockRescanLanes = 4;
+constexpr int kBlockRescanPart = 32 / kBlockRescanLanes;   // 8 points
+
+__device__ __forceinline__ void rescan_block(const float *__restrict__ stream, int blk, int rl, int E, float cx,
+                                             float cy, float &best, int &bidx)
+{
+    const int j0 = 32 * blk + rl * kBlockRescanPart;   // first point of the part
+    const float *col = stream + kChunkFloats * (blk >> 2) + 32 * (blk & 3) + rl * kBlockRescanPart;
+    const float4 *px = (const float4 *)col, *py = (const float4 *)(col + kChunk);
+    const int n = E - j0;   // points of this part inside the stream
+#pragma unroll
+    for (int b = 0; b < kBlockRescanPart / 4; ++b) {
+        const float4 X = px[b], Y = py[b];
+        const float xs[4] = {X.x, X.y, X.z, X.w}, ys[4] = {Y.x, Y.y, Y.z, Y.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = 4 * b + k;
+            const float d = edge_d2(xs[k], ys[k], cx, cy);
+            if (j < n && d < best) {
+                best = d;
+                bidx = j0 + j;
+            }
+        }
     }
 }
 

@@ -327,6 +327,33 @@ constexpr size_t scan_lds_bytes(int G, int CW)
     return (size_t)kStageBytes * G * CW + (size_t)G * 256 * CW * 20 + (size_t)256 * CW * 4 + 16;
 }
 
+// Objects per group of the fused rollout's pruned scan (offroad_unit_pruned):
+// a wave scans for the 4 kGroupObjects corners of a group at a time.
+constexpr int kGroupObjects = 4;
+// Road-edge chunks whose boxes (chunk and block boxes, 80 bytes per chunk)
+// the fused rollout copies into LDS; a scenario with more reads them from
+// global memory.
+constexpr int kLdsBoxChunks = 256;
+
+// LDS of the pruned scan: per wave kPruneWaveBytes, the five candidate
+// arrays of SL = 256 CW corner slots, the slots of the exact scan, then two
+// counters (exact-scan slots, claimed groups); a region of at least
+// `floor` bytes (the IDM lead search shares it).
+__device__ __forceinline__ ScanLds carve_scan_pruned(void *p, int G, int CW)
+{
+    float4 *stage = (float4 *)p;
+    float *f = (float *)((unsigned char *)p + (size_t)kPruneWaveBytes * G * CW);
+    const int SL = 256 * CW;
+    int *fl = (int *)(f + 5 * SL);
+    return ScanLds{stage, f, f + SL, f + 2 * SL, (int *)(f + 3 * SL), (int *)(f + 4 * SL), fl, fl + SL};
+}
+
+__host__ __device__ constexpr size_t scan_pruned_lds_bytes(int G, int CW, size_t floor)
+{
+    const size_t b = (size_t)kPruneWaveBytes * G * CW + (size_t)256 * CW * 24 + 16;
+    return b > floor ? b : align_up(floor, 16);
+}
+
 template <int R>
 __device__ __forceinline__ void scan_r(const float *stream, int c0, int c1, float4 *stage, const float (&cx)[4],
                                        const float (&cy)[4],
@@ -561,85 +588,78 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
     }
 }
 
-// The fused rollout's off-road step for slice objects i0 .. i0+Ns-1 (the
-// result of offroad_unit, with the scan pruned).  The unit's objects are
-// taken in `order` (spatial order, see spatial_order) in groups of 16 R:
-// W = blockDim / 64 waves form NG = min(W, Ns_max / 16) groups; the
-// W / NG waves of a group split its chunks; a lane holds corner (lane & 3) of
-// the group's objects (lane >> 2) + 16 r, r < R.  prevj[slot] (slot = 4 il +
-// corner) is the corner's nearest stream point of the previous step (-1:
-// none), whose distance bounds what the scan must look at (scan_edges_pruned);
-// this step's nearest point replaces it.
-template <int R>
-__device__ void offroad_group_scan(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
-                                   const float4 *__restrict__ cbox, const float4 *__restrict__ box, int E,
-                                   float qqmax, int NG, int splits, const ScanLds &C, int SL, const int *order,
-                                   const int *prevj)
+// The pruned scan of one step for the slice objects i0 .. i0+Ns-1, taken
+// in `order` (spatial order, see spatial_order) in groups of GO: the waves
+// claim groups from the counter *gctr (zero at entry) until none is left.
+// prevq[slot] (slot = 4 il + corner) is the corner's nearest road-edge point
+// of the previous step ((+inf, +inf): none), whose distance bounds what the
+// scan must look at (scan_group_pruned).  Writes the candidate arrays of C
+// (one split) for every slot of the slice.
+template <int GO>
+__device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
+                               const float4 *cbox, const float4 *box, int E, float qqmax, const ScanLds &C,
+                               const int *order, const float2 *prevq, int *gctr)
 {
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int sg = w % NG, g = w / NG;
+    constexpr int CL = 16 / GO;   // lanes per corner
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nch = (E + kChunk - 1) / kChunk;
-    const int cps = (nch + splits - 1) / splits;
-    const int c0 = min(nch, g * cps), c1 = min(nch, c0 + cps);
-    float cx[R], cy[R], thr[R], b1[R], b2[R], b3[R];
-    int i1[R], i2[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int rank = 16 * R * sg + (lane >> 2) + 16 * r;
+    const int ngroups = (Ns + GO - 1) / GO;
+    float4 *stage = (float4 *)((unsigned char *)C.stage + (long)w * kPruneWaveBytes);
+    uint16_t *list = (uint16_t *)(stage + kPruneStageBytes / 16);
+    const int k = lane / CL;   // corner of the group: object k / 4, corner k % 4
+    for (;;) {
+        int gi = 0;
+        if (lane == 0)
+            gi = atomicAdd(gctr, 1);
+        gi = __builtin_amdgcn_readfirstlane(gi);
+        if (gi >= ngroups)
+            break;
+        const int rank = gi * GO + (k >> 2);
         const int il = rank < Ns ? order[rank] : -1;
         const int o = i0 + max(il, 0);
-        box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], lane & 3, cx[r], cy[r]);
-        thr[r] = -__builtin_inff();   // needs nothing
+        float cx, cy;
+        box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], k & 3, cx, cy);
+        float thr = -__builtin_inff();   // needs nothing
         if (il >= 0 && L.valid[o]) {
-            const int j = prevj[4 * il + (lane & 3)];
-            thr[r] = __builtin_inff();
-            if (j >= 0) {
-                const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
-                thr[r] = edge_d2(ch[0], ch[kChunk], cx[r], cy[r]) + 2.0f * candidate_band(qqmax, cx[r], cy[r]);
-            }
+            const float2 q = prevq[4 * il + (k & 3)];
+            thr = edge_d2(q.x, q.y, cx, cy) + 2.0f * candidate_band(qqmax, cx, cy);
         }
-        b1[r] = b2[r] = b3[r] = __builtin_inff();
-        i1[r] = i2[r] = -1;
-    }
-    float4 *stage = C.stage + (long)w * (kStageBytes / 16);
-    if (c0 < c1)
-        scan_edges_pruned<R>(stream, cbox, box, c0, c1, stage, cx, cy, thr, b1, b2, b3, i1, i2);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int rank = 16 * R * sg + (lane >> 2) + 16 * r;
-        if (rank < Ns) {
-            const int at = g * SL + 4 * order[rank] + (lane & 3);
-            C.b1[at] = b1[r];
-            C.b2[at] = b2[r];
-            C.b3[at] = b3[r];
-            C.i1[at] = i1[r];
-            C.i2[at] = i2[r];
+        float b1 = __builtin_inff(), b2 = __builtin_inff(), b3 = __builtin_inff();
+        int i1 = -1, i2 = -1;
+        scan_group_pruned<GO>(stream, cbox, box, nch, stage, list, cx, cy, thr, b1, b2, b3, i1, i2);
+        if (il >= 0 && lane % CL == 0) {
+            const int at = 4 * il + (k & 3);
+            C.b1[at] = b1;
+            C.b2[at] = b2;
+            C.b3[at] = b3;
+            C.i1[at] = i1;
+            C.i2[at] = i2;
         }
     }
 }
 
+// The fused rollout's off-road step for slice objects i0 .. i0+Ns-1 (the
+// result of offroad_unit, with the scan pruned: offroad_groups).  prevq
+// receives this step's nearest points.  *gctr must be zero at entry; it is
+// zero again at return.
 __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, const float *__restrict__ stream,
                                     const float2 *__restrict__ edir, const int32_t *__restrict__ eidx,
-                                    const float4 *__restrict__ cbox, const float4 *__restrict__ box, int E,
-                                    float qqmax, ScanLds C, float *sk, int *nidx, const int *order, int *prevj)
+                                    const float4 *cbox, const float4 *box, int E, float qqmax, ScanLds C, float *sk,
+                                    int *nidx, const int *order, float2 *prevq, int *gctr)
 {
     const int tid = threadIdx.x, lane = tid & 63;
-    const int W = blockDim.x >> 6;
-    const int NG = min(W, U / 16), splits = W / NG, R = U / (16 * NG);
+    const int splits = 1;
     const int SL = 4 * U;
     const int nslots = 4 * Ns;
     if (tid == 0)
         *C.nfull = 0;
-    if (R == 1)
-        offroad_group_scan<1>(L, i0, Ns, stream, cbox, box, E, qqmax, NG, splits, C, SL, order, prevj);
-    else if (R == 2)
-        offroad_group_scan<2>(L, i0, Ns, stream, cbox, box, E, qqmax, NG, splits, C, SL, order, prevj);
-    else
-        offroad_group_scan<4>(L, i0, Ns, stream, cbox, box, E, qqmax, NG, splits, C, SL, order, prevj);
+    offroad_groups<kGroupObjects>(L, i0, Ns, stream, cbox, box, E, qqmax, C, order, prevq, gctr);
     __syncthreads();
+    if (tid == 0)
+        *gctr = 0;
     for (int slot = tid; slot < nslots; slot += blockDim.x) {
-        // best chunk over the splits (ascending splits hold ascending chunks)
+        // best block (one split)
         float b = __builtin_inff();
         int bc = -1;
         for (int h = 0; h < splits; ++h) {
@@ -650,13 +670,13 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
             }
         }
         const int o = i0 + (slot >> 2);
-        int lo = -1, hi = -1;   // candidate chunks; lo: -1 none, -2 the exact scan of every point
+        int lo = -1, hi = -1;   // candidate blocks; lo: -1 none, -2 the exact scan of every point
         if (bc >= 0 && L.valid[o]) {
             float x, y;
             box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
             const float lim = b + candidate_band(qqmax, x, y);
-            int other = -1;        // a second candidate chunk
-            bool full = false;     // three or more candidates: exact scan of every chunk
+            int other = -1;        // a second candidate block
+            bool full = false;     // three or more candidates: exact scan of every point
             for (int h = 0; h < splits; ++h) {
                 const int at = h * SL + slot;
                 if (C.b3[at] <= lim)
@@ -684,8 +704,8 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
         sk[slot] = __int_as_float(hi);
     }
     __syncthreads();
-    for (int u0 = 0; u0 < nslots * kRescanLanes; u0 += blockDim.x) {   // block-uniform trip count
-        const int u = u0 + tid, slot = u / kRescanLanes, rl = u % kRescanLanes;
+    for (int u0 = 0; u0 < nslots * kBlockRescanLanes; u0 += blockDim.x) {   // block-uniform trip count
+        const int u = u0 + tid, slot = u / kBlockRescanLanes, rl = u % kBlockRescanLanes;
         const bool act = slot < nslots;
         const int lo = act ? nidx[slot] : -1, hi = act ? __float_as_int(sk[slot]) : -1;
         float best = __builtin_inff(), x = 0.f, y = 0.f;
@@ -693,11 +713,11 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
         if (lo >= 0) {
             const int o = i0 + (slot >> 2);
             box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
-            rescan_part(stream, lo, rl, E, x, y, best, bj);
+            rescan_block(stream, lo, rl, E, x, y, best, bj);
             if (hi >= 0)
-                rescan_part(stream, hi, rl, E, x, y, best, bj);
+                rescan_block(stream, hi, rl, E, x, y, best, bj);
         }
-        for (int off = kRescanLanes / 2; off > 0; off >>= 1) {
+        for (int off = kBlockRescanLanes / 2; off > 0; off >>= 1) {
             const float ob = __shfl_xor(best, off);
             const int oj = __shfl_xor(bj, off);
             if (ob < best || (ob == best && oj < bj)) {
@@ -707,17 +727,18 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
         }
         if (act && rl == 0) {
             float s_val = kNoValue;
-            int near = -1, pj = -1;
+            int near = -1;
+            float2 pq = make_float2(__builtin_inff(), __builtin_inff());
             if (lo >= 0 && bj != 0x7fffffff) {
                 const float *ch = stream + kChunkFloats * (bj / kChunk) + (bj % kChunk);
                 const float qx = ch[0], qy = ch[kChunk];
                 const float2 d = edir[bj];
                 s_val = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
                 near = eidx[bj];
-                pj = bj;
+                pq = make_float2(qx, qy);
             }
             if (lo != -2)
-                prevj[slot] = pj;
+                prevq[slot] = pq;
             sk[slot] = s_val;
             nidx[slot] = near;
         }
@@ -772,14 +793,16 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
                     b = C.b1[v];
                     j = C.i1[v];
                 }
+            float2 pq = make_float2(__builtin_inff(), __builtin_inff());
             if (j != 0x7fffffff) {
                 const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
                 const float qx = ch[0], qy = ch[kChunk];
                 const float2 d = edir[j];
                 sk[slot] = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
                 nidx[slot] = eidx[j];
+                pq = make_float2(qx, qy);
             }
-            prevj[slot] = j != 0x7fffffff ? j : -1;
+            prevq[slot] = pq;
         }
         __syncthreads();
     }
@@ -787,7 +810,7 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
 
 // Spatial order of slice objects i0 .. i0+Ns-1: ascending by the Morton code
 // of their 8 m cell (invalid objects last), ties by index, into order[].
-// Neighbouring objects then share the waves of the pruned scan.  Two
+// Neighbouring objects then share the groups of the pruned scan.  Two
 // barriers.
 __device__ __forceinline__ void spatial_order(const ObjLds &L, int i0, int Ns, uint32_t *key, int *order)
 {
@@ -804,14 +827,18 @@ __device__ __forceinline__ void spatial_order(const ObjLds &L, int i0, int Ns, u
         key[il] = k;
     }
     __syncthreads();
-    for (int il = threadIdx.x; il < Ns; il += blockDim.x) {
+    // eight lanes per object, each counting the keys j = part (mod 8) below it
+    const int part = threadIdx.x & 7;
+    for (int il = threadIdx.x >> 3; il < Ns; il += blockDim.x >> 3) {
         const uint32_t k = key[il];
         int rank = 0;
-        for (int j = 0; j < Ns; ++j) {
+        for (int j = part; j < Ns; j += 8) {
             const uint32_t kj = key[j];
             rank += (kj < k || (kj == k && j < il)) ? 1 : 0;
         }
-        order[rank] = il;
+        rank = lanes_sum8(rank);
+        if (part == 0)
+            order[rank] = il;
     }
     __syncthreads();
 }
@@ -1020,8 +1047,14 @@ constexpr int kIdmMaskMaxN = 256;
 // to WM_MAX_IDM_POSES lookahead poses, then the candidate list (ints).
 constexpr int kIdmPoseScratch = 3 * 64;
 static_assert(WM_MAX_IDM_POSES <= 64, "one lane per lookahead pose");
-static_assert((kIdmPoseScratch + WM_MAX_OBJECTS) * 4 <= kStageBytes + 256 * 20,
-              "poses and candidates of a wave fit in that wave's share of the off-road scratch");
+
+// The fused rollout's scan region in LDS: the pruned scan's, at least as
+// large as the lead search's per-wave scratch (poses and a candidate list of
+// maxN) for every wave.
+__host__ __device__ constexpr size_t rollout_scan_bytes(int G, int CW, int maxN)
+{
+    return scan_pruned_lds_bytes(G, CW, (size_t)G * CW * (kIdmPoseScratch + maxN) * 4);
+}
 
 __device__ __forceinline__ int wave_min(int v)
 {
@@ -1081,7 +1114,7 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
     }
     // a wave's share of the scratch: poses, candidate list, then (when it
     // fits) the agent's path arc lengths for an LDS search
-    const int per_wave = (int)(scan_lds_bytes(A.G, A.CW) / 4 / nw);
+    const int per_wave = (int)(rollout_scan_bytes(A.G, A.CW, A.maxN) / 4 / nw);
     float *px = wscr + (size_t)wv * per_wave, *py = px + 64, *pyw = px + 128;
     int *cl = (int *)(px + kIdmPoseScratch);
     float *wcol = px + kIdmPoseScratch + A.maxN;
@@ -1248,8 +1281,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int SL = 256 * A.CW;
     const int nthr = blockDim.x;
     const int P = nthr / U;
-    const ScanLds C = carve_scan(p, A.G, SL);
-    float *sk = (float *)(p + scan_lds_bytes(A.G, A.CW));
+    const ScanLds C = carve_scan_pruned(p, A.G, A.CW);
+    float *sk = (float *)(p + rollout_scan_bytes(A.G, A.CW, A.maxN));
     int *nidx = (int *)(sk + SL);
     float *red = (float *)(nidx + SL);
     float *wsum = red + nthr;
@@ -1259,11 +1292,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     uint8_t *agent = (uint8_t *)(lk + A.maxN);
     float *pc = (float *)(agent + align_up((size_t)A.maxN, 16));   // IDM: pose at sig (x, y)
     uint32_t *mask = (uint32_t *)(pc + 2 * A.maxN);                   // IDM: candidate bit masks
-    // the pruned off-road scan: spatial keys and order of the slice's
-    // objects, each corner's nearest stream point of the previous step
-    uint32_t *okey = (uint32_t *)align_up((size_t)(mask + (A.maxN <= kIdmMaskMaxN ? A.maxN * ((A.maxN + 31) / 32) : 0)), 16);
+    // the pruned off-road scan: the scenario's chunk and block boxes (when at
+    // most kLdsBoxChunks chunks), each corner's nearest road-edge point of the
+    // previous step, spatial keys and order of the slice's objects, the
+    // group counter
+    float4 *lcbox = (float4 *)align_up((size_t)(mask + (A.maxN <= kIdmMaskMaxN ? A.maxN * ((A.maxN + 31) / 32) : 0)), 16);
+    float4 *lbox = lcbox + kLdsBoxChunks;
+    float2 *prevq = (float2 *)(lbox + 4 * kLdsBoxChunks);
+    uint32_t *okey = (uint32_t *)(prevq + 4 * U);
     int *order = (int *)(okey + U);
-    int *prevj = order + U;
+    int *gctr = order + U;
     __shared__ int s_unit;
     const int tid = threadIdx.x;
     const long n = A.n;
@@ -1298,7 +1336,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int il = tid; il < Ns; il += nthr)
                 store_object(L, i0 + il, A.ckpt, o0 + i0 + il);
         for (int k = tid; k < 4 * U; k += nthr)
-            prevj[k] = -1;
+            prevq[k] = make_float2(__builtin_inff(), __builtin_inff());
+        const int nch = (E + kChunk - 1) / kChunk;
+        const bool lds_boxes = nch <= kLdsBoxChunks;
+        if (lds_boxes) {
+            for (int k = tid; k < nch; k += nthr)
+                lcbox[k] = A.E.cbox[eb / kChunk + k];
+            for (int k = tid; k < 4 * nch; k += nthr)
+                lbox[k] = A.E.box[eb / kBoxPts + k];
+        }
+        if (tid == 0)
+            *gctr = 0;
         __syncthreads();
         float my_loss = 0.f;
         for (int t = 1; t <= A.T; ++t) {
@@ -1347,8 +1395,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (A.has_rg) {
                 spatial_order(L, i0, Ns, okey, order);
                 offroad_unit_pruned(L, i0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb,
-                                    A.E.cbox + eb / kChunk, A.E.box + eb / kBoxPts, E, qqmax, C, sk, nidx, order,
-                                    prevj);
+                                    lds_boxes ? lcbox : A.E.cbox + eb / kChunk,
+                                    lds_boxes ? lbox : A.E.box + eb / kBoxPts, E, qqmax, C, sk, nidx, order, prevq,
+                                    gctr);
             } else {
                 __syncthreads();
             }
@@ -1476,8 +1525,10 @@ size_t rollout_lds_bytes(int maxN, int G, int CW)
     const int nthr = 64 * CW * G;
     const size_t idm = (size_t)maxN * 12 + align_up((size_t)maxN, 16) + (size_t)maxN * 8 +
                        (maxN <= kIdmMaskMaxN ? (size_t)maxN * ((maxN + 31) / 32) * 4 : 0);
-    const size_t prune = (size_t)64 * CW * 24 + 16;   // keys, order, previous nearest points
-    return objects_lds(maxN) + offroad_scratch(G, CW) + (size_t)nthr * 4 + 16 * 4 + align_up(idm, 16) + prune;
+    // boxes, previous nearest points, keys, order, group counter
+    const size_t prune = (size_t)kLdsBoxChunks * 80 + (size_t)64 * CW * 40 + 16 + 16;
+    return objects_lds(maxN) + rollout_scan_bytes(G, CW, maxN) + (size_t)256 * CW * 8 + (size_t)nthr * 4 + 16 * 4 +
+           align_up(idm, 16) + prune;
 }
 
 void launch_idm_paths(int n, int T, const wm_state &log, const uint8_t *controlled, float4 *path, uint8_t *agent,
