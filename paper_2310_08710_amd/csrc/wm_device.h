@@ -401,11 +401,12 @@ __device__ __forceinline__ float box_lb(const float4 bb, float cx, float cy)
 
 // The pruned scan (scan_group_pruned) stages up to kPruneBatch blocks at a
 // time per wave; a staged block is its 32 points' x, y and qq, 8 float4 each
-// (kBlockF4).  Per wave it also lists the needed blocks (kPruneList 16-bit
+// (kBlockF4), and one more float4 takes the writes of the lanes that load
+// nothing.  Per wave it also lists the needed blocks (kPruneList 16-bit
 // entries).
 constexpr int kPruneBatch = 8;
 constexpr int kBlockF4 = 24;
-constexpr int kPruneStageBytes = kPruneBatch * kBlockF4 * 16;
+constexpr int kPruneStageBytes = (kPruneBatch * kBlockF4 + 1) * 16;
 constexpr int kPruneList = 512;
 constexpr int kPruneWaveBytes = kPruneStageBytes + kPruneList * 2;
 
@@ -535,18 +536,29 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
     const bool loader = half < 2;
     int seg = 0;    // list entries are 4 (chunk - seg) + block
     int nl = 0;
-    float4 v[kPruneBatch / 2];
-    // slot s of a batch from b0: blocks b0 + 2 s (lanes 0..23) and b0 + 2 s + 1 (lanes 24..47)
-    auto fetch = [&](int b0, int nb) {
-#pragma unroll
-        for (int s = 0; s < kPruneBatch / 2; ++s) {
-            const int i = 2 * s + half;
-            if (loader && i < nb) {
-                const int e = list[b0 + i];
-                v[s] = src[(long)kChunkF4 * (seg + (e >> 2)) + (e & 3) * 8 + poff];
-            }
-        }
+    // the batch in flight: slot s holds blocks 2 s (lanes 0..23) and 2 s + 1
+    // (lanes 24..47) of the batch (four named slots, so that they stay in
+    // registers)
+    static_assert(kPruneBatch == 8, "four load slots");
+    float4 v0, v1, v2, v3;
+    // every lane loads (those without a block of their own the batch's
+    // first one again), so that no lane-dependent branch leaves a load
+    // pending
+    auto load_slot = [&](int b0, int nb, int s) -> float4 {
+        const int i = 2 * s + half;
+        const int e = list[b0 + (loader && i < nb ? i : 0)];
+        return src[(long)kChunkF4 * (seg + (e >> 2)) + (e & 3) * 8 + poff];
     };
+    auto fetch = [&](int b0, int nb) {
+        v0 = load_slot(b0, nb, 0);
+        if (nb > 2)
+            v1 = load_slot(b0, nb, 1);
+        if (nb > 4)
+            v2 = load_slot(b0, nb, 2);
+        if (nb > 6)
+            v3 = load_slot(b0, nb, 3);
+    };
+    const int sl = loader ? lane : kPruneBatch * kBlockF4;   // this lane's stage slot (or the spare float4)
     auto fold_list = [&]() {
         __builtin_amdgcn_wave_barrier();
         if (nl == 0)
@@ -554,10 +566,13 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
         fetch(0, min(kPruneBatch, nl));
         for (int b0 = 0; b0 < nl; b0 += kPruneBatch) {
             const int nb = min(kPruneBatch, nl - b0);
-#pragma unroll
-            for (int s = 0; s < kPruneBatch / 2; ++s)
-                if (loader && 2 * s < nb)
-                    stage[2 * kBlockF4 * s + lane] = v[s];
+            stage[sl] = v0;
+            if (nb > 2)
+                stage[loader ? 2 * kBlockF4 + sl : sl] = v1;
+            if (nb > 4)
+                stage[loader ? 4 * kBlockF4 + sl : sl] = v2;
+            if (nb > 6)
+                stage[loader ? 6 * kBlockF4 + sl : sl] = v3;
             if (b0 + kPruneBatch < nl)
                 fetch(b0 + kPruneBatch, min(kPruneBatch, nl - b0 - kPruneBatch));
             __builtin_amdgcn_wave_barrier();
