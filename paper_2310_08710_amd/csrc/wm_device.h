@@ -432,6 +432,21 @@ __device__ __forceinline__ float lanes_min(float v)
     return v;
 }
 
+// Maximum over the 16 lanes of a DPP row, in every lane of it.
+template <int Ctrl>
+__device__ __forceinline__ float dpp_max(float v)
+{
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false)));
+}
+
+__device__ __forceinline__ float lanes_max16(float v)
+{
+    v = dpp_max<0xB1>(v);
+    v = dpp_max<0x4E>(v);
+    v = dpp_max<0x141>(v);
+    return dpp_max<0x140>(v);
+}
+
 // Sum over the lanes of a group of 8 consecutive lanes, in every lane of it.
 template <int Ctrl>
 __device__ __forceinline__ int dpp_add(int v)
@@ -484,19 +499,23 @@ __device__ __forceinline__ void fold_part(const float4 *st, int part, float m2x,
 // needs nothing.
 //
 // The tests run with a box per lane: per pass of 64 chunks, lane j tests
-// chunk box j against every corner (broadcast from its lanes), then lane l
-// tests block l & 3 of the (l >> 2)-th needed chunk, 16 needed chunks at a
-// time; the needed blocks are listed in ascending order and fetched
+// chunk box j against every object of the group (broadcast from its lanes):
+// its centre (ox, oy) and the radius orad of the circle through its corners
+// give a bound that every corner's test implies (below); then lane l tests
+// block l & 3 of the (l >> 2)-th chunk that passed, 16 such chunks at a
+// time, against every corner; the needed blocks are listed in ascending
+// order and fetched
 // kPruneBatch at a time, two per 16-byte load (lanes 0..47), the next batch
 // in flight while one is folded from `stage`.  cbox and box may point to
 // global memory or to a copy in LDS.
 template <int GO>
 __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stream, const float4 *cbox,
                                                   const float4 *box, int nch, float4 *stage, uint16_t *list,
-                                                  float cx, float cy, float thr, float &b1, float &b2, float &b3,
-                                                  int &i1, int &i2)
+                                                  float cx, float cy, float thr, float ox, float oy, float orad,
+                                                  float &b1, float &b2, float &b3, int &i1, int &i2)
 {
     constexpr int NC = 4 * GO, CL = 64 / NC, PL = 32 / CL;
+    static_assert(NC * CL == 64 && 4 * CL == 16, "an object's corners fill one DPP row of 16 lanes");
     constexpr int kChunkF4 = kStageBytes / 16;   // float4 per chunk in the stream
     static_assert(kChunk == 4 * 32 && kChunkF4 == 3 * 32, "four blocks of 32 points per chunk");
     static_assert(PL % 4 == 0, "whole groups of four points per lane");
@@ -513,6 +532,32 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
             const float kx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cx), k * CL));
             const float ky = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cy), k * CL));
             const float kt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(thr), k * CL));
+            a |= box_lb(b, kx, ky) <= kt;
+        }
+        return a;
+    };
+    // The object bound.  A corner c passes box B when box_lb(B, c) <= thr_c;
+    // then the exact distance d(B, c) <= sqrt(thr_c) (1 + 2 eps) (box_lb
+    // rounds its three operations down by at most a factor (1 - eps)^3), so
+    // d(B, centre) <= d(B, c) + |c - centre| <= sqrt(thr_max) (1 + 2 eps) +
+    // orad + (rounding of the corner), and box_lb(B, centre) is at most
+    // (1 + eps)^3 times its square.  The relative 2^-10 and the absolute
+    // 1e-3 m + 2^-20 (|ox| + |oy|) margins cover all of these, and a chunk
+    // box contains its blocks' boxes, so a chunk failing the bound has no
+    // block any corner needs.
+    const float tmax = lanes_max16(thr);
+    float othr = -__builtin_inff();
+    if (tmax >= 0.f) {
+        const float rr = sqrtf(tmax) * (1.0f + 0x1p-10f) + orad + 1e-3f + 0x1p-20f * (fabsf(ox) + fabsf(oy));
+        othr = rr * rr;
+    }
+    auto any_object = [&](const float4 b) -> bool {
+        bool a = false;
+#pragma unroll
+        for (int j = 0; j < GO; ++j) {
+            const float kx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ox), 16 * j));
+            const float ky = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(oy), 16 * j));
+            const float kt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(othr), 16 * j));
             a |= box_lb(b, kx, ky) <= kt;
         }
         return a;
@@ -593,9 +638,9 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
             seg = base;
         const int cnt = min(64, nch - base);
         const float4 cb = lane < cnt ? cbox[base + lane] : empty;
-        // bit j: chunk base + j has a needed point (lanes past the range hold
-        // an empty box, which a corner with thr = +inf would pass)
-        uint64_t cm = __ballot(lane < cnt && any_corner(cb));
+        // bit j: chunk base + j may hold a needed point (lanes past the range
+        // hold an empty box, which a corner with thr = +inf would pass)
+        uint64_t cm = __ballot(lane < cnt && any_object(cb));
         while (cm != 0) {
             // lane l: block (l & 3) of the (l >> 2)-th needed chunk of this batch
             int myc = -1;

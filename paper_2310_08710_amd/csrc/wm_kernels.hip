@@ -627,7 +627,9 @@ __device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__r
         }
         float b1 = __builtin_inff(), b2 = __builtin_inff(), b3 = __builtin_inff();
         int i1 = -1, i2 = -1;
-        scan_group_pruned<GO>(stream, cbox, box, nch, stage, list, cx, cy, thr, b1, b2, b3, i1, i2);
+        const float orad = 0.5f * sqrtf(__builtin_fmaf(L.wid[o], L.wid[o], L.len[o] * L.len[o]));
+        scan_group_pruned<GO>(stream, cbox, box, nch, stage, list, cx, cy, thr, L.x[o], L.y[o], orad, b1, b2, b3,
+                              i1, i2);
         if (il >= 0 && lane % CL == 0) {
             const int at = 4 * il + (k & 3);
             C.b1[at] = b1;
