@@ -319,6 +319,17 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
                wm_state *ckpt, wm_state *traj, wm_metrics *met_seq, float *loss, const wm_tuning *tune,
                void *ws, size_t ws_bytes, void *stream);
 
+/* Work counts of the off-road scan of the last wm_rollout or wm_rollout_idm
+ * run with workspace `ws` (same batch), for measurement: counts[0] road-edge
+ * blocks of 32 points folded (each for the 16 corners of a group of four
+ * objects, so 512 corner-point evaluations), counts[1] chunk bounding boxes
+ * tested against an object's circle, counts[2] block bounding boxes tested
+ * against a corner (Sec. 3.4 Off-Road; the pruning is this library's, the
+ * metric is unchanged).  `counts` is host memory [3]; the call waits for
+ * `stream` to finish.  Errors: NULL pointers, a workspace smaller than the
+ * counters' offset. */
+int wm_rollout_scan_counts(const wm_batch *batch, const void *ws, size_t ws_bytes, uint64_t *counts, void *stream);
+
 /* IDM sim agents (Sec. 3.5, simulated agent behaviour; intelligent driver
  * model of Treiber, Hennecke and Helbing 2000).  Field units: m, s. */
 typedef struct wm_idm {

@@ -640,6 +640,27 @@ int wm_rollout(const wm_batch *batch, const wm_state *init, const wm_action *act
                         tune, ws, ws_bytes, stream);
 }
 
+int wm_rollout_scan_counts(const wm_batch *batch, const void *ws, size_t ws_bytes, uint64_t *counts, void *stream)
+{
+    CHECK(check_batch(batch));
+    if (!ws || !counts)
+        return fail(WM_ERR_NULL, "wm_rollout_scan_counts: ws or counts is NULL");
+    // the queue counters sit before every section that depends on T or the
+    // checkpoint interval
+    const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
+    const size_t at = L.counter + sizeof(int32_t) * wm::kRollCounts;
+    if (ws_bytes < at + sizeof(uint64_t) * wm::kRollCountN)
+        return fail(WM_ERR_WORKSPACE, "wm_rollout_scan_counts: workspace of %zu bytes is too small", ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(counts, (const unsigned char *)ws + at, sizeof(uint64_t) * wm::kRollCountN,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return fail(WM_ERR_DEVICE, "wm_rollout_scan_counts: %s", hipGetErrorString(e));
+    return ok();
+}
+
 int wm_rollout_idm(const wm_batch *batch, const wm_state *init, const wm_action *act_seq, const wm_state *log_seq,
                    const wm_roadgraph *rg, int32_t T, float dt, const wm_idm *idm, wm_state *traj,
                    wm_metrics *met_seq, const wm_tuning *tune, void *ws, size_t ws_bytes, void *stream)

@@ -508,11 +508,18 @@ __device__ __forceinline__ void fold_part(const float4 *st, int part, float m2x,
 // kPruneBatch at a time, two per 16-byte load (lanes 0..47), the next batch
 // in flight while one is folded from `stage`.  cbox and box may point to
 // global memory or to a copy in LDS.
+// Work counts of the pruned scan (wave-uniform): blocks folded, chunk boxes
+// tested against an object, block boxes tested against a corner.
+struct ScanCounts {
+    uint32_t folded, chunk_tests, block_tests;
+};
+
 template <int GO>
 __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stream, const float4 *cbox,
                                                   const float4 *box, int nch, float4 *stage, uint16_t *list,
                                                   float cx, float cy, float thr, float ox, float oy, float orad,
-                                                  float &b1, float &b2, float &b3, int &i1, int &i2)
+                                                  float &b1, float &b2, float &b3, int &i1, int &i2,
+                                                  ScanCounts &work)
 {
     constexpr int NC = 4 * GO, CL = 64 / NC, PL = 32 / CL;
     static_assert(NC * CL == 64 && 4 * CL == 16, "an object's corners fill one DPP row of 16 lanes");
@@ -608,6 +615,7 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
         __builtin_amdgcn_wave_barrier();
         if (nl == 0)
             return;
+        work.folded += nl;
         fetch(0, min(kPruneBatch, nl));
         for (int b0 = 0; b0 < nl; b0 += kPruneBatch) {
             const int nb = min(kPruneBatch, nl - b0);
@@ -641,15 +649,18 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
         // bit j: chunk base + j may hold a needed point (lanes past the range
         // hold an empty box, which a corner with thr = +inf would pass)
         uint64_t cm = __ballot(lane < cnt && any_object(cb));
+        work.chunk_tests += GO * cnt;
         while (cm != 0) {
             // lane l: block (l & 3) of the (l >> 2)-th needed chunk of this batch
             int myc = -1;
-            for (int nb = 0; nb < 16 && cm != 0; ++nb) {
+            int nb = 0;
+            for (; nb < 16 && cm != 0; ++nb) {
                 const int j = __builtin_ctzll(cm);
                 cm &= cm - 1;
                 if ((lane >> 2) == nb)
                     myc = base + j;
             }
+            work.block_tests += NC * 4 * nb;
             const float4 bb = myc >= 0 ? box[4 * myc + (lane & 3)] : empty;
             const uint64_t bm = __ballot(myc >= 0 && any_corner(bb));   // bit l: lane l's block is needed
             const int below =

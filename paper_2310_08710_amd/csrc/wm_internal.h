@@ -127,6 +127,12 @@ struct BackwardArgs {
     float *part;     // [T][n][4] pair-term sums per step and controlled object
 };
 
+// The queue counter area (16 int32): [0] next unit, [1] units; from int32
+// index kRollCounts, kRollCountN 64-bit work counts of the fused rollout's
+// off-road scan (wm_rollout_scan_counts).
+constexpr int kRollCounts = 4;
+constexpr int kRollCountN = 3;
+
 // Workspace rows of the adjoint's recursion inputs per step and object.
 constexpr int kRecFields = 16;
 

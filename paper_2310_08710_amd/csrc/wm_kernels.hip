@@ -197,6 +197,8 @@ __global__ __launch_bounds__(1024) void k_build_units(const int32_t *__restrict_
         counter[0] = 0;
         counter[1] = total;
     }
+    if (tid < 2 * kRollCountN)
+        counter[kRollCounts + tid] = 0;
     // costs
     for (int s = tid; s < S; s += 1024) {
         const int N = obj_off[s + 1] - obj_off[s];
@@ -598,7 +600,7 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
 template <int GO>
 __device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
                                const float4 *cbox, const float4 *box, int E, float qqmax, const ScanLds &C,
-                               const int *order, const float2 *prevq, int *gctr)
+                               const int *order, const float2 *prevq, int *gctr, ScanCounts &work)
 {
     constexpr int CL = 16 / GO;   // lanes per corner
     const int lane = threadIdx.x & 63;
@@ -629,7 +631,7 @@ __device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__r
         int i1 = -1, i2 = -1;
         const float orad = 0.5f * sqrtf(__builtin_fmaf(L.wid[o], L.wid[o], L.len[o] * L.len[o]));
         scan_group_pruned<GO>(stream, cbox, box, nch, stage, list, cx, cy, thr, L.x[o], L.y[o], orad, b1, b2, b3,
-                              i1, i2);
+                              i1, i2, work);
         if (il >= 0 && lane % CL == 0) {
             const int at = 4 * il + (k & 3);
             C.b1[at] = b1;
@@ -648,7 +650,7 @@ __device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__r
 __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, const float *__restrict__ stream,
                                     const float2 *__restrict__ edir, const int32_t *__restrict__ eidx,
                                     const float4 *cbox, const float4 *box, int E, float qqmax, ScanLds C, float *sk,
-                                    int *nidx, const int *order, float2 *prevq, int *gctr)
+                                    int *nidx, const int *order, float2 *prevq, int *gctr, ScanCounts &work)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int splits = 1;
@@ -656,7 +658,7 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
     const int nslots = 4 * Ns;
     if (tid == 0)
         *C.nfull = 0;
-    offroad_groups<kGroupObjects>(L, i0, Ns, stream, cbox, box, E, qqmax, C, order, prevq, gctr);
+    offroad_groups<kGroupObjects>(L, i0, Ns, stream, cbox, box, E, qqmax, C, order, prevq, gctr, work);
     __syncthreads();
     if (tid == 0)
         *gctr = 0;
@@ -1307,6 +1309,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ int s_unit;
     const int tid = threadIdx.x;
     const long n = A.n;
+    ScanCounts work{0u, 0u, 0u};
     for (;;) {
         if (tid == 0)
             s_unit = atomicAdd(A.counter, 1);
@@ -1314,8 +1317,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         // the unit, its scenario and the scan's chunk ranges are made provably
         // wave-uniform (scalar registers)
         const int q = __builtin_amdgcn_readfirstlane(s_unit);
-        if (q >= __builtin_amdgcn_readfirstlane(A.counter[1]))
+        if (q >= __builtin_amdgcn_readfirstlane(A.counter[1])) {
+            // this wave's work counts (kRollCounts after the queue counters)
+            if ((tid & 63) == 0) {
+                unsigned long long *wc = (unsigned long long *)(A.counter + kRollCounts);
+                atomicAdd(wc, (unsigned long long)work.folded);
+                atomicAdd(wc + 1, (unsigned long long)work.chunk_tests);
+                atomicAdd(wc + 2, (unsigned long long)work.block_tests);
+            }
             break;
+        }
         const int2 un = A.units[q];
         const int s = __builtin_amdgcn_readfirstlane(un.x), slice = __builtin_amdgcn_readfirstlane(un.y);
         const int o0 = __builtin_amdgcn_readfirstlane(A.obj_off[s]);
@@ -1399,7 +1410,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                 offroad_unit_pruned(L, i0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb,
                                     lds_boxes ? lcbox : A.E.cbox + eb / kChunk,
                                     lds_boxes ? lbox : A.E.box + eb / kBoxPts, E, qqmax, C, sk, nidx, order, prevq,
-                                    gctr);
+                                    gctr, work);
             } else {
                 __syncthreads();
             }

@@ -118,6 +118,7 @@ def lib() -> C.CDLL:
         L.wm_rollout_idm.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction), C.POINTER(CState),
                                      C.POINTER(CRoadgraph), C.c_int32, C.c_float, C.POINTER(CIdm),
                                      C.POINTER(CState), C.POINTER(CMetrics), C.POINTER(CTuning), _P, C.c_size_t, _P]
+        L.wm_rollout_scan_counts.argtypes = [C.POINTER(CBatch), _P, C.c_size_t, C.POINTER(C.c_uint64), _P]
         L.wm_rollout_backward.argtypes = [C.POINTER(CBatch), C.POINTER(CState), C.POINTER(CAction),
                                           C.POINTER(CState), C.c_int32, C.c_float, C.c_int32, C.POINTER(CState),
                                           _P, _P, _P, _P, C.c_size_t, _P]
@@ -513,6 +514,16 @@ def rollout_idm(batch: Batch, init: State, act_seq: Action, log_seq: State, rg: 
                                 T, dt, C.byref(p), C.byref(tr) if tr is not None else None,
                                 C.byref(m) if m is not None else None, _tune(tune), ws.data_ptr(), ws.numel(),
                                 _stream(stream)))
+
+
+def rollout_scan_counts(batch: Batch, ws: torch.Tensor, stream=None):
+    """Work counts of the last fused rollout run with workspace ws: (blocks
+    folded, chunk-box object tests, block-box corner tests); waits for the
+    stream."""
+    _need(ws, 0, torch.uint8, "ws", False)
+    out = (C.c_uint64 * 3)()
+    _check(lib().wm_rollout_scan_counts(C.byref(batch.c()), ws.data_ptr(), ws.numel(), out, _stream(stream)))
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def rollout_backward(batch: Batch, init: State, act_seq: Action, log_seq: State, T: int, dt: float, ckpt_every: int,

@@ -325,3 +325,15 @@ def test_binding_rejects_short_or_mistyped_tensors():
     with pytest.raises(ValueError, match="batch.obj_off"):
         bad = wm.Batch(b.obj_off.to(torch.int64), b.rg_off, 2, n, P, 4, 12)
         wm.step(bad, good, act, good, None, 0.1, _cpu_state(n))
+
+
+def test_scan_counts_validation():
+    """wm_rollout_scan_counts rejects NULL pointers and a workspace that ends
+    before its counters, before touching the device."""
+    lib = wm.lib()
+    b = _batch()
+    out = (C.c_uint64 * 3)()
+    assert lib.wm_rollout_scan_counts(C.byref(b), None, 1 << 20, out, None) == wm.WM_ERR_NULL
+    assert lib.wm_rollout_scan_counts(C.byref(b), FAKE, 1 << 20, None, None) == wm.WM_ERR_NULL
+    assert lib.wm_rollout_scan_counts(C.byref(b), FAKE, 16, out, None) == wm.WM_ERR_WORKSPACE
+    assert lib.wm_rollout_scan_counts(None, FAKE, 1 << 20, out, None) == wm.WM_ERR_NULL

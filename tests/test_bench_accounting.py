@@ -82,3 +82,22 @@ def test_algorithmic_adjoint_pairs():
     valid[100] = 0
     _, pairs = bench.adjoint_algorithmic_ops(off[:2], ctrl[:128], valid[:128], 1)
     assert pairs == 7 * 125 - 21          # 126 valid objects, 7 of them controlled
+
+
+class _Scene:
+    def __init__(self, counts):
+        self.obj_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+
+
+def test_rollout_executed_ops():
+    """The fused rollout's executed work from its counts: 512 corner-point
+    pairs (32 points x 16 corners) at 6 ops per folded block, 10 ops per box
+    test, and the same overlap, dynamics and displacement terms as the
+    algorithmic count."""
+    sc = _Scene([3, 5])
+    ops, pairs = bench.rollout_executed_ops(sc, 2, (0, 0, 0))
+    rest = 2 * (3 * (20 * 2 + 35) + 5 * (20 * 4 + 35))
+    assert pairs == 0 and ops == rest
+    ops, pairs = bench.rollout_executed_ops(sc, 2, (7, 11, 13))
+    assert pairs == 7 * 512
+    assert ops == 6 * 7 * 512 + 10 * (11 + 13) + rest
