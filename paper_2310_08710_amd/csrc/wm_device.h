@@ -132,6 +132,23 @@ __device__ __forceinline__ float sat_margin(const Box &a, const Box &b)
     return fminf(fminf(g1, g2), fminf(g3, g4));
 }
 
+// sat_margin(a, b) when a_first, else sat_margin(b, a), in one evaluation:
+// swapping the boxes negates the offsets exactly and commutes the operands
+// of every other product, so the two orders differ only in the rounding of
+// |sin(yaw_b - yaw_a)|; the four gaps swap places, and the minimum of the
+// same four values is taken.
+__device__ __forceinline__ float sat_margin_ordered(const Box &a, const Box &b, bool a_first)
+{
+    const float dx = b.x - a.x, dy = b.y - a.y;
+    const float C = fabsf(__builtin_fmaf(a.c, b.c, a.s * b.s));
+    const float S = a_first ? fabsf(__builtin_fmaf(a.c, b.s, -(a.s * b.c))) : fabsf(__builtin_fmaf(b.c, a.s, -(b.s * a.c)));
+    const float g1 = a.hl + __builtin_fmaf(b.hl, C, b.hw * S) - fabsf(__builtin_fmaf(dx, a.c, dy * a.s));
+    const float g2 = a.hw + __builtin_fmaf(b.hl, S, b.hw * C) - fabsf(__builtin_fmaf(dy, a.c, -(dx * a.s)));
+    const float g3 = b.hl + __builtin_fmaf(a.hl, C, a.hw * S) - fabsf(__builtin_fmaf(dx, b.c, dy * b.s));
+    const float g4 = b.hw + __builtin_fmaf(a.hl, S, a.hw * C) - fabsf(__builtin_fmaf(dy, b.c, -(dx * b.s)));
+    return fminf(fminf(g1, g2), fminf(g3, g4));
+}
+
 // ---------------------------------------------------------------------------
 // IDM sim agents (Sec. 3.5; intelligent driver model).  An agent's path is
 // its logged positions, rows 0..T of the log window, with cumulative arc
@@ -416,7 +433,9 @@ constexpr int kPruneWaveBytes = kPruneStageBytes + kPruneList * 2;
 template <int Ctrl>
 __device__ __forceinline__ float dpp_min(float v)
 {
-    return fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false)));
+    // every lane's source lane exists in these patterns, so bound_ctrl
+    // changes nothing but spares the move of a default value
+    return fminf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Ctrl, 0xF, 0xF, true)));
 }
 
 template <int CL>
@@ -436,7 +455,7 @@ __device__ __forceinline__ float lanes_min(float v)
 template <int Ctrl>
 __device__ __forceinline__ float dpp_max(float v)
 {
-    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false)));
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Ctrl, 0xF, 0xF, true)));
 }
 
 __device__ __forceinline__ float lanes_max16(float v)
@@ -451,7 +470,7 @@ __device__ __forceinline__ float lanes_max16(float v)
 template <int Ctrl>
 __device__ __forceinline__ int dpp_add(int v)
 {
-    return v + __builtin_amdgcn_update_dpp(0, v, Ctrl, 0xF, 0xF, false);
+    return v + __builtin_amdgcn_mov_dpp(v, Ctrl, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ int lanes_sum8(int v)

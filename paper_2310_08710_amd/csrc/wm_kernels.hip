@@ -286,14 +286,15 @@ __device__ __forceinline__ void overlap_partial(const ObjLds &L, int N, int i0, 
     if (il < Ns) {
         const bool vi = L.valid[i];
         const Box bi = lds_box(L, i);
+        // every pair is evaluated (operands in index order) and the invalid
+        // ones masked, so that the loop carries no branches
         for (int j = part; j < N; j += P) {
-            float m = kNoValue;
-            if (vi && j != i && L.valid[j]) {
-                const Box bj = lds_box(L, j);
-                m = i < j ? sat_margin(bi, bj) : sat_margin(bj, bi);
-                if (loss && j > i && (L.ctrl[i] || L.ctrl[j]))
-                    *loss += sigmoidf(m * (1.0f / kSoftScale));
-            }
+            const Box bj = lds_box(L, j);
+            const float mm = sat_margin_ordered(bi, bj, i < j);   // sat_margin in index order
+            const bool use = vi && j != i && L.valid[j];
+            const float m = use ? mm : kNoValue;
+            if (loss && use && j > i && (L.ctrl[i] || L.ctrl[j]))
+                *loss += sigmoidf(m * (1.0f / kSoftScale));
             if (row_margin)
                 row_margin[(long)il * N + j] = m;
             if (row_mask)
@@ -698,6 +699,8 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
             }
             if (full) {
                 C.full[atomicAdd(C.nfull, 1)] = slot;
+                // the exact scan's bound on D (b is a minimum of T = D - |c|^2)
+                C.b3[slot] = (b + __builtin_fmaf(y, y, x * x)) + candidate_band(qqmax, x, y);
                 lo = -2;
             } else {
                 lo = other >= 0 ? min(bc, other) : bc;
@@ -755,27 +758,19 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
         const int o = i0 + (slot >> 2);
         float x, y;
         box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+        // The exact scan of every block that can hold the nearest point: the
+        // point of smallest T (= D - |c|^2 in exact arithmetic) has D within a
+        // quarter band of b1 + |c|^2, so the minimum of D is at most that, and
+        // a block whose box_lb exceeds lim = b1 + |c|^2 + band (the band also
+        // covers the rounding of the sum) holds no point at the minimum.
+        const float lim = C.b3[slot];
         float best = __builtin_inff();
         int bj = 0x7fffffff;
-        for (int j0 = tid; j0 < E; j0 += 8 * nthr) {
-            float px[8], py[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = min(j0 + u * nthr, E - 1);
-                const float *ch = stream + kChunkFloats * (j / kChunk) + (j % kChunk);
-                px[u] = ch[0];
-                py[u] = ch[kChunk];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = j0 + u * nthr;
-                const float d = edge_d2(px[u], py[u], x, y);
-                if (j < E && d < best) {
-                    best = d;
-                    bj = j;
-                }
-            }
-        }
+        const int nblk = (E + 31) / 32;
+        for (int k = tid; k < nblk; k += nthr)
+            if (box_lb(box[k], x, y) <= lim)
+                for (int q = 0; q < kBlockRescanLanes; ++q)
+                    rescan_block(stream, k, q, E, x, y, best, bj);
         for (int off = 32; off > 0; off >>= 1) {
             const float ob = __shfl_xor(best, off);
             const int oj = __shfl_xor(bj, off);

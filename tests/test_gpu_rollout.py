@@ -511,3 +511,53 @@ def test_largest_scenario_fused_equals_plain_and_oracle():
                          sc.dt)
     gm = {f: getattr(met, f).cpu().numpy() for f in METRICS}
     compare_rollout(traj.numpy(), gm, loss.cpu().numpy(), ref, sc.obj_off, sc.rg_off, f64(sc.rg))
+
+
+@pytest.mark.gpu
+def test_fused_rollout_exact_scan_of_tied_corners():
+    """A tiny stationary object whose four corners all sit within a millimetre
+    of (302, 201), where four road-edge points in four different 32-point
+    blocks lie at distance 5: every corner has three or more candidate blocks
+    within the band, so the fused rollout takes its exact scan for all four
+    corners at every step, and the object's off-road margin comes only from
+    that path.  The scene sits away from the origin, so that |corner|^2 (the
+    offset between the scan's expanded form and the squared distance) is much
+    larger than the band.  Compared with the oracle step by step (playback,
+    so the states are the logged ones)."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    P, T = 320, 3
+    xy = np.stack([1300.0 + np.arange(P), 1200.0 + 0.5 * np.arange(P)], 1)
+    ring = [(305, 205), (299, 197), (306, 204), (298, 198)]          # distance 5 from (302, 201)
+    positions = (10, 160, 230, 300)
+    for k, pos in enumerate(positions):
+        xy[pos] = ring[k]
+    ang = np.arange(P) * 0.1
+    rg = {"x": xy[:, 0], "y": xy[:, 1], "dir_x": np.cos(ang), "dir_y": np.sin(ang),
+          "type": np.ones(P, np.int8), "valid": np.ones(P, np.uint8)}
+    n = 2
+    row = {"x": np.array([302.0, 330.0]), "y": np.array([201.0, 160.0]), "yaw": np.array([0.0, 0.7]),
+           "vx": np.zeros(n), "vy": np.zeros(n), "length": np.array([0.002, 4.5]),
+           "width": np.array([0.002, 1.9]), "valid": np.ones(n, np.uint8)}
+    obj_off = np.array([0, n], np.int32)
+    rg_off = np.array([0, P], np.int32)
+    batch = wm.Batch.from_offsets(obj_off, rg_off, dev)
+
+    def rows(v, dtype):
+        return torch.tensor(np.tile(np.asarray(v), (T + 1, 1)), dtype=dtype, device=dev)
+
+    log = wm.State(*[rows(row[f], torch.float32) for f in wm.STATE_FIELDS], rows(row["valid"], torch.uint8))
+    init = wm.State(*[getattr(log, f)[0].clone() for f in wm.STATE_FIELDS], log.valid[0].clone())
+    act = wm.Action(torch.zeros((T, n), device=dev), torch.zeros((T, n), device=dev),
+                    torch.zeros(n, dtype=torch.uint8, device=dev))
+    met = wm.Metrics.empty((T, n), dev)
+    traj = wm.State.empty((T, n), dev)
+    ws = batch.workspace(T, 0)
+    wm.rollout(batch, init, act, log, wm.Roadgraph.from_numpy(rg, dev), T, 0.1, ws, traj=traj, metrics=met)
+    torch.cuda.synchronize()
+    ref = oracle.offroad(obj_off, rg_off, row, rg)
+    for t in range(T):
+        np.testing.assert_array_equal(met.offroad[t].cpu().numpy(), ref["offroad"])
+        np.testing.assert_allclose(met.offroad_margin[t].cpu().numpy(), ref["margin"], rtol=1e-5, atol=1e-4)
+    assert met.offroad_margin[0, 0].item() != wm.NO_VALUE
