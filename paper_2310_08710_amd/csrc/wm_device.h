@@ -588,10 +588,9 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
         }
         return a;
     };
-    float m = __builtin_inff();
-    // m (this lane's part) becomes the minimum of block blk
-    auto flush = [&](int cur) {
-        const float mm = lanes_min<CL>(m);
+
+    // block cur's minimum mm (over all its lanes) into the three smallest
+    auto push = [&](float mm, int cur) {
         const bool lt1 = mm < b1, lt2 = mm < b2;
         b3 = __builtin_amdgcn_fmed3f(b2, b3, mm);
         b2 = __builtin_amdgcn_fmed3f(b1, b2, mm);
@@ -599,7 +598,6 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
         const int j2 = lt2 ? cur : i2;
         i2 = lt1 ? i1 : j2;
         i1 = lt1 ? cur : i1;
-        m = __builtin_inff();
     };
     // this lane's piece of a block: column (x, y, qq) piece / 8, float4 piece % 8
     const int half = lane / kBlockF4, piece = lane % kBlockF4;
@@ -649,9 +647,17 @@ __device__ __forceinline__ void scan_group_pruned(const float *__restrict__ stre
                 fetch(b0 + kPruneBatch, min(kPruneBatch, nl - b0 - kPruneBatch));
             __builtin_amdgcn_wave_barrier();
             const int ent = lane < nb ? (int)list[b0 + lane] : 0;   // the batch's entries, one per lane
-            for (int i = 0; i < nb; ++i) {
-                fold_part<PL>(stage + kBlockF4 * i, part, m2x, m2y, m);
-                flush(4 * seg + __builtin_amdgcn_readlane(ent, i));
+            // two blocks at a time (for an odd count the second is a stale stage
+            // slot, folded but not pushed)
+            for (int i = 0; i < nb; i += 2) {
+                float ma = __builtin_inff(), mb = __builtin_inff();
+                fold_part<PL>(stage + kBlockF4 * i, part, m2x, m2y, ma);
+                fold_part<PL>(stage + kBlockF4 * (i + 1), part, m2x, m2y, mb);
+                ma = lanes_min<CL>(ma);
+                mb = lanes_min<CL>(mb);
+                push(ma, 4 * seg + __builtin_amdgcn_readlane(ent, i));
+                if (i + 1 < nb)
+                    push(mb, 4 * seg + __builtin_amdgcn_readlane(ent, i + 1));
             }
             __builtin_amdgcn_wave_barrier();
         }
