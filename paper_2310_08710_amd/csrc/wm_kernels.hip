@@ -28,53 +28,79 @@ namespace wm {
 // as x[], y[], qq[] columns of kEdgeChunk points, plus their directions, original indices, count and
 // the largest qq (it bounds the rounding of the scan's expanded distance).
 // ---------------------------------------------------------------------------
-template <int BT>
+// One work-group per scenario.  A round covers PPT sub-rounds of BT
+// consecutive points (sub-round k: point j0 + k BT + thread); the waves'
+// ballot counts of every sub-round are prefix-summed in (sub-round, wave)
+// order by the first wave, so a round costs two barriers and every load is
+// coalesced.  A scenario of 30,000 points takes four rounds.
+template <int BT, int PPT>
 __global__ __launch_bounds__(BT) void k_compact_edges(const int32_t *__restrict__ rg_off, wm_roadgraph rg, Edges E)
 {
-    __shared__ int wave_tot[BT / 64];
-    __shared__ int run;
+    constexpr int NW = BT / 64, NC = PPT * NW;
+    static_assert(NC <= 128, "two counts per lane of the first wave");
+    __shared__ int cnt_k[NC], off_k[NC + 1];
     __shared__ unsigned int qqmax_bits;
     const int s = blockIdx.x;
     const int p0 = rg_off[s], p1 = rg_off[s + 1];
     const long base = edge_base(p0, s);                // first point slot of the scenario
     float *stream = E.stream + 3 * base;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) {
-        run = 0;
+    if (threadIdx.x == 0)
         qqmax_bits = 0u;
-    }
     __syncthreads();
     float my_max = 0.f;
-    for (int j0 = p0; j0 < p1; j0 += BT) {
-        const int j = j0 + threadIdx.x;
-        const bool f = j < p1 && rg.valid[j] && rg.type[j] == WM_TYPE_ROAD_EDGE;
-        const uint64_t m = __ballot(f);
-        const int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0)
-            wave_tot[w] = __popcll(m);
-        __syncthreads();
-        int off = run, total = 0;
-        for (int i = 0; i < BT / 64; ++i) {
-            off += (i < w) ? wave_tot[i] : 0;
-            total += wave_tot[i];
-        }
-        if (f) {
-            const int o = off + pre;
-            const float x = rg.x[j], y = rg.y[j];
-            const float qq = __builtin_fmaf(y, y, x * x);
-            float *ch = stream + kChunkFloats * (o / kChunk);
-            ch[o % kChunk] = x;
-            ch[kChunk + o % kChunk] = y;
-            ch[2 * kChunk + qq_slot(o % kChunk)] = qq;
-            E.dir[base + o] = make_float2(rg.dir_x[j], rg.dir_y[j]);
-            E.idx[base + o] = j - p0;
-            my_max = fmaxf(my_max, qq);
+    int run = 0;   // edges of the earlier rounds (the same in every thread)
+    for (int j0 = p0; j0 < p1; j0 += BT * PPT) {
+        uint64_t m[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int j = j0 + k * BT + threadIdx.x;
+            m[k] = __ballot(j < p1 && rg.valid[j] && rg.type[j] == WM_TYPE_ROAD_EDGE);
+            if (lane == 0)
+                cnt_k[k * NW + w] = __popcll(m[k]);
         }
         __syncthreads();
-        if (threadIdx.x == 0)
-            run += total;
+        if (w == 0) {
+            // exclusive prefix of the NC counts, two per lane
+            const int a = 2 * lane < NC ? cnt_k[2 * lane] : 0;
+            const int b = 2 * lane + 1 < NC ? cnt_k[2 * lane + 1] : 0;
+            int incl = a + b;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int v = __shfl_up(incl, d);
+                if (lane >= d)
+                    incl += v;
+            }
+            const int excl = incl - a - b;
+            if (2 * lane < NC)
+                off_k[2 * lane] = excl;
+            if (2 * lane + 1 < NC)
+                off_k[2 * lane + 1] = excl + a;
+            if (lane == 63)
+                off_k[NC] = incl;
+        }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if ((m[k] >> lane) & 1ull) {
+                const int j = j0 + k * BT + threadIdx.x;
+                const int below =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[k], 0));
+                const int o = run + off_k[k * NW + w] + below;
+                const float x = rg.x[j], y = rg.y[j];
+                const float qq = __builtin_fmaf(y, y, x * x);
+                float *ch = stream + kChunkFloats * (o / kChunk);
+                ch[o % kChunk] = x;
+                ch[kChunk + o % kChunk] = y;
+                ch[2 * kChunk + qq_slot(o % kChunk)] = qq;
+                E.dir[base + o] = make_float2(rg.dir_x[j], rg.dir_y[j]);
+                E.idx[base + o] = j - p0;
+                my_max = fmaxf(my_max, qq);
+            }
+        }
+        run += off_k[NC];
     }
+    __syncthreads();
     atomicMax(&qqmax_bits, __float_as_uint(my_max));   // qq >= 0: bit order = value order
     const int cnt = run;
     const int padded = (cnt + kChunk - 1) / kChunk * kChunk;
@@ -1475,7 +1501,8 @@ static size_t objects_lds(int maxN) { return align_up((size_t)maxN * 39, 16); }
 void launch_compact_edges(const wm_batch &b, const wm_roadgraph &rg, unsigned char *ws, const WsLayout &L,
                           hipStream_t st)
 {
-    hipLaunchKernelGGL(k_compact_edges<256>, dim3(b.num_scenarios), dim3(256), 0, st, b.rg_off, rg, ws_edges(ws, L));
+    hipLaunchKernelGGL((k_compact_edges<1024, 8>), dim3(b.num_scenarios), dim3(1024), 0, st, b.rg_off, rg,
+                       ws_edges(ws, L));
 }
 
 void launch_edge_boxes(const wm_batch &b, unsigned char *ws, const WsLayout &L, hipStream_t st)
