@@ -378,17 +378,94 @@ __device__ __forceinline__ RevStep rev_load(const BackwardArgs &A, int t, long g
     return RevStep{((const float4 *)A.part)[at], r[0], r[1], r[2], r[3]};
 }
 
+// One step of the reverse recursion for one controlled object: the log and
+// pair terms of step t, then the bicycle adjoint back to step t - 1.
+__device__ __forceinline__ void rev_step(const BackwardArgs &A, const RevStep &cur, int t, long g, float w,
+                                         float &bx, float &by, float &byaw, float &bvx, float &bvy)
+{
+    const float dt = A.dt, hdt2 = 0.5f * dt * dt;
+    const long n = A.n;
+    bx += w * cur.p.x;
+    by += w * cur.p.y;
+    byaw += w * cur.p.z;
+    if (cur.r1.z != 0.f) {   // log term, where the log is valid
+        bx += w * 2.f * (cur.r0.x - cur.r1.x);
+        by += w * 2.f * (cur.r0.y - cur.r1.y);
+    }
+    // factors from the previous state (t - 1) and the action of step t
+    const float nc = cur.r0.z, ns = cur.r0.w, c0 = cur.r1.w, s0 = cur.r2.x;
+    const float nv = cur.r2.y, k = cur.r2.z, dist = cur.r2.w;
+    const float ahdt2 = cur.r3.x, ux = cur.r3.y, uy = cur.r3.z;
+    const float bnv = __builtin_fmaf(bvx, nc, bvy * ns);
+    const float tyaw = byaw + nv * __builtin_fmaf(bvy, nc, -(bvx * ns));
+    const float ga_ = __builtin_fmaf(hdt2, __builtin_fmaf(bx, c0, __builtin_fmaf(by, s0, k * tyaw)), dt * bnv);
+    const float gk_ = dist * tyaw;
+    const float pyaw = tyaw + ahdt2 * __builtin_fmaf(by, c0, -(bx * s0));
+    const float bv = __builtin_fmaf(k * dt, tyaw, bnv);
+    A.grad_a[(long)(t - 1) * n + g] = ga_;
+    A.grad_k[(long)(t - 1) * n + g] = gk_;
+    byaw = pyaw;
+    bvx = __builtin_fmaf(dt, bx, bv * ux);
+    bvy = __builtin_fmaf(dt, by, bv * uy);
+}
+
+// Scenarios with at most 64 controlled objects (one wave of the recursion):
+// the other waves stage the inputs of a chunk of steps in LDS, two buffers
+// of kRevStage bytes, while the first wave runs the recursion over the
+// previous chunk from LDS.
+constexpr int kRevStage = 24576;
+constexpr int kRevF4 = 5;   // float4 per (step, object): pair sums + 4 of the record
+
 __global__ __launch_bounds__(kRevThreads) void k_bwd_reverse(BackwardArgs A)
 {
     __shared__ int cidx[WM_MAX_OBJECTS];
     __shared__ int wcnt[kRevThreads / 64];
+    extern __shared__ __align__(16) float4 rstage[];
     const int s = blockIdx.x;
     const int o0 = A.obj_off[s], N = A.obj_off[s + 1] - o0;
-    const long n = A.n;
     const int NC = live_objects(A, o0, N, cidx, wcnt);
     const float w = A.dloss[s];
-    const float dt = A.dt, hdt2 = 0.5f * dt * dt;
     const int T = A.T;
+    if (NC == 0)
+        return;
+    if (NC <= 64 && kRevThreads >= 128) {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int C = max(1, min(T, kRevStage / (16 * kRevF4 * NC)));   // steps per chunk
+        const int nchunk = (T + C - 1) / C;
+        const long n = A.n;
+        // chunk c holds steps t = T - c C down to max(1, T - (c + 1) C + 1):
+        // element (u, q, r) at ((u * NC + q) * kRevF4 + r) of its buffer
+        auto stage_chunk = [&](int c, int first, int stride) {
+            float4 *buf = rstage + (long)(c & 1) * (kRevStage / 16);
+            const int thi = T - c * C, nstep = min(C, thi);
+            const int items = nstep * NC * kRevF4;
+            for (int e = first; e < items; e += stride) {
+                const int r = e % kRevF4, uq = e / kRevF4, q = uq % NC, u = uq / NC;
+                const long at = (long)(thi - u - 1) * n + o0 + cidx[q];
+                buf[e] = r == 0 ? ((const float4 *)A.part)[at] : ((const float4 *)A.rec)[4 * at + (r - 1)];
+            }
+        };
+        stage_chunk(0, threadIdx.x, kRevThreads);
+        __syncthreads();
+        float bx = 0.f, by = 0.f, byaw = 0.f, bvx = 0.f, bvy = 0.f;
+        const long g = lane < NC ? o0 + cidx[lane] : 0;
+        for (int c = 0; c < nchunk; ++c) {
+            if (wv > 0) {
+                if (c + 1 < nchunk)
+                    stage_chunk(c + 1, threadIdx.x - 64, kRevThreads - 64);
+            } else if (lane < NC) {
+                const float4 *buf = rstage + (long)(c & 1) * (kRevStage / 16);
+                const int thi = T - c * C, nstep = min(C, thi);
+                for (int u = 0; u < nstep; ++u) {
+                    const float4 *e = buf + (u * NC + lane) * kRevF4;
+                    const RevStep cur{e[0], e[1], e[2], e[3], e[4]};
+                    rev_step(A, cur, thi - u, g, w, bx, by, byaw, bvx, bvy);
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
     for (int q = threadIdx.x; q < NC; q += kRevThreads) {
         const long g = o0 + cidx[q];
         // the adjoint of the object's (x, y, yaw, vx, vy)
@@ -406,29 +483,7 @@ __global__ __launch_bounds__(kRevThreads) void k_bwd_reverse(BackwardArgs A)
                 const RevStep cur = ring[u];
                 if (t - kRevDepth >= 1)   // in flight while the next steps run
                     ring[u] = rev_load(A, t - kRevDepth, g);
-                bx += w * cur.p.x;
-                by += w * cur.p.y;
-                byaw += w * cur.p.z;
-                if (cur.r1.z != 0.f) {   // log term, where the log is valid
-                    bx += w * 2.f * (cur.r0.x - cur.r1.x);
-                    by += w * 2.f * (cur.r0.y - cur.r1.y);
-                }
-                // factors from the previous state (t - 1) and the action of step t
-                const float nc = cur.r0.z, ns = cur.r0.w, c0 = cur.r1.w, s0 = cur.r2.x;
-                const float nv = cur.r2.y, k = cur.r2.z, dist = cur.r2.w;
-                const float ahdt2 = cur.r3.x, ux = cur.r3.y, uy = cur.r3.z;
-                const float bnv = __builtin_fmaf(bvx, nc, bvy * ns);
-                const float tyaw = byaw + nv * __builtin_fmaf(bvy, nc, -(bvx * ns));
-                const float ga_ =
-                    __builtin_fmaf(hdt2, __builtin_fmaf(bx, c0, __builtin_fmaf(by, s0, k * tyaw)), dt * bnv);
-                const float gk_ = dist * tyaw;
-                const float pyaw = tyaw + ahdt2 * __builtin_fmaf(by, c0, -(bx * s0));
-                const float bv = __builtin_fmaf(k * dt, tyaw, bnv);
-                A.grad_a[(long)(t - 1) * n + g] = ga_;
-                A.grad_k[(long)(t - 1) * n + g] = gk_;
-                byaw = pyaw;
-                bvx = __builtin_fmaf(dt, bx, bv * ux);
-                bvy = __builtin_fmaf(dt, by, bv * uy);
+                rev_step(A, cur, t, g, w, bx, by, byaw, bvx, bvy);
             }
         }
     }
@@ -458,7 +513,7 @@ void launch_backward(const BackwardArgs &a, hipStream_t st)
         (void)hipFuncSetAttribute((const void *)k_bwd_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int nblk = (a.T + a.SB - 1) / a.SB;
     hipLaunchKernelGGL(k_bwd_pairs, dim3((unsigned)((long)a.S * nblk)), dim3(kPairThreads), lds, st, a);
-    hipLaunchKernelGGL(k_bwd_reverse, dim3(a.S), dim3(kRevThreads), 0, st, a);
+    hipLaunchKernelGGL(k_bwd_reverse, dim3(a.S), dim3(kRevThreads), 2 * kRevStage, st, a);
 }
 
 } // namespace wm
