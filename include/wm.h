@@ -389,8 +389,12 @@ int wm_rollout_backward(const wm_batch *batch, const wm_state *init, const wm_ac
 
 /* Measure the rollout for each candidate tuning on this batch (real launches
  * on `stream`, synchronizing) and remember the fastest for batches with the
- * same (max_objects, max_rg_points) bucket.  best (host) receives it; may be
- * NULL.  Not capturable. */
+ * same (max_objects, max_rg_points) bucket (power-of-two buckets).  best
+ * (host) receives it; may be NULL.  Not capturable.  With the environment
+ * variable WM_TUNE_CACHE naming a file, the pick is appended to that file
+ * (one text line per device kind and bucket) and a later process takes a
+ * matching line instead of timing again, also for a NULL tuning argument of
+ * the rollout calls. */
 int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *act_seq,
                 const wm_state *log_seq, const wm_roadgraph *rg, int32_t T, float dt, void *ws,
                 size_t ws_bytes, wm_tuning *best, void *stream);

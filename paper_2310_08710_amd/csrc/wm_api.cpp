@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -110,6 +112,72 @@ struct Tune {
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, Tune> g_tune_table;
 
+// Tunings kept across processes: with WM_TUNE_CACHE naming a file, every
+// tuning wm_autotune picks is appended to it as a line
+//   wm-tune <version> <arch> <compute units> <object bucket> <point bucket> <unit_objects> <edge_splits>
+// and a later process takes the last matching line instead of timing again
+// (wm_autotune) or of the default (a NULL tuning).  The version changes with
+// the rollout kernel's work layout, so that older lines stop matching.
+constexpr int kTuneCacheVersion = 3;
+
+std::string tune_device_tag()
+{
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos)
+            arch = arch.substr(0, colon);   // gfx950, without the feature flags
+    }
+    return arch + " " + std::to_string(cus);
+}
+
+// The cached tuning of bucket `key` on this device, from the file WM_TUNE_CACHE.
+bool tune_cache_lookup(std::pair<int, int> key, Tune *out)
+{
+    const char *path = std::getenv("WM_TUNE_CACHE");
+    if (!path || !*path)
+        return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return false;
+    const std::string dev = tune_device_tag();
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char arch[64];
+        int ver = 0, cus = 0, ob = 0, pb = 0, U = 0, G = 0;
+        if (std::sscanf(line, "wm-tune %d %63s %d %d %d %d %d", &ver, arch, &cus, &ob, &pb, &U, &G) != 7)
+            continue;
+        if (ver != kTuneCacheVersion || std::string(arch) + " " + std::to_string(cus) != dev ||
+            ob != key.first || pb != key.second)
+            continue;
+        if ((U != 64 && U != 128 && U != 256) || (G != 1 && G != 2 && G != 4 && G != 8 && G != 16) || U * G > 512)
+            continue;
+        *out = Tune{G, U / 64};   // the last matching line wins
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_store(std::pair<int, int> key, const wm_tuning &t)
+{
+    const char *path = std::getenv("WM_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f, "wm-tune %d %s %d %d %d %d\n", kTuneCacheVersion, tune_device_tag().c_str(), key.first,
+                 key.second, t.unit_objects, t.edge_splits);
+    std::fclose(f);
+}
+
 std::pair<int, int> tune_key(const wm_batch *b)
 {
     int ob = 0, pb = 0;
@@ -136,12 +204,16 @@ int resolve_tune(const wm_batch *b, const wm_tuning *t, int max_threads, Tune *o
         return WM_OK;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_table.find(tune_key(b));
+    const std::pair<int, int> key = tune_key(b);
+    auto it = g_tune_table.find(key);
     if (it != g_tune_table.end()) {
         *out = it->second;
     } else {
-        out->G = 8;
-        out->CW = 1;
+        if (!tune_cache_lookup(key, out)) {
+            out->G = 8;
+            out->CW = 1;
+        }
+        g_tune_table[key] = *out;   // the cache file is read once per bucket
     }
     return WM_OK;
 }
@@ -728,6 +800,17 @@ int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *ac
     CHECK(rollout_checks(batch, init, act_seq, log_seq, T, dt, 0));
     const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, T, 0);
     CHECK(check_ws(ws, ws_bytes, L.total));
+    {
+        // a tuning kept by an earlier process (WM_TUNE_CACHE) is taken as is
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        Tune cached;
+        if (tune_cache_lookup(tune_key(batch), &cached)) {
+            g_tune_table[tune_key(batch)] = cached;
+            if (best)
+                *best = wm_tuning{64 * cached.CW, cached.G};
+            return ok();
+        }
+    }
     static const int cand[][2] = {{64, 2}, {64, 4}, {64, 8}, {128, 1}, {128, 2}, {128, 4}, {256, 1}, {256, 2}};
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -764,6 +847,7 @@ int wm_autotune(const wm_batch *batch, const wm_state *init, const wm_action *ac
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_table[tune_key(batch)] = Tune{pick.edge_splits, pick.unit_objects / 64};
+        tune_cache_store(tune_key(batch), pick);
     }
     if (best)
         *best = pick;

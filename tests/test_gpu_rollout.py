@@ -561,3 +561,31 @@ def test_fused_rollout_exact_scan_of_tied_corners():
         np.testing.assert_array_equal(met.offroad[t].cpu().numpy(), ref["offroad"])
         np.testing.assert_allclose(met.offroad_margin[t].cpu().numpy(), ref["margin"], rtol=1e-5, atol=1e-4)
     assert met.offroad_margin[0, 0].item() != wm.NO_VALUE
+
+
+@pytest.mark.gpu
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    """With WM_TUNE_CACHE set, wm_autotune appends its pick to the file, and a
+    matching line (same device kind and batch bucket) is taken without timing:
+    a planted line for this batch's bucket is returned as is."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = _ragged(T=4)
+    ds = wm.upload(sc, dev)
+    T = sc.steps
+    ws = ds.batch.workspace(T, 0)
+    prop = torch.cuda.get_device_properties(0)
+    tag = "%s %d" % (prop.gcnArchName.split(":")[0], prop.multi_processor_count)
+    ob = max(int(sc.max_objects - 1).bit_length(), 0)
+    pb = max(int(sc.max_rg_points - 1).bit_length(), 0)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("WM_TUNE_CACHE", str(path))
+    picked = wm.autotune(ds.batch, ds.init, ds.act_seq, ds.log_seq, ds.rg, T, sc.dt, ws)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    assert lines[0].split() == ["wm-tune", "3"] + tag.split() + [str(ob), str(pb), str(picked[0]), str(picked[1])]
+    planted = (128, 2) if tuple(picked) != (128, 2) else (64, 4)
+    path.write_text("wm-tune 3 %s %d %d %d %d\n" % (tag, ob, pb, planted[0], planted[1]))
+    assert tuple(wm.autotune(ds.batch, ds.init, ds.act_seq, ds.log_seq, ds.rg, T, sc.dt, ws)) == planted
+    assert len(path.read_text().splitlines()) == 1   # taken, not timed and appended
