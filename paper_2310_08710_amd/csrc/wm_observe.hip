@@ -519,23 +519,23 @@ __device__ __forceinline__ void observe_exact_item(const ObserveArgs &A, int row
 // Egos whose bin b holds more than kBndCap keys, or a lower bin more than
 // kBinRankCap (many equal or nearly equal keys), are handed to the exact
 // kernel above: their first rg_idx place is set to kHandOver and nothing else
-// is written for them here.  Work-groups are small (two waves, 26 KB of LDS)
-// so that six of them, each with its own ego, share a CU.
+// is written for them here.  Work-groups are small (four waves, 26 KB of LDS)
+// so that four of them, each with its own ego, share a CU.
 // ---------------------------------------------------------------------------
-constexpr int kFastThreads = 128;
+constexpr int kFastThreads = 256;
 constexpr int kFastWaves = kFastThreads / 64;
 constexpr int kBlockPts = 32;
 // blocks start at multiples of 8 global points, so a scenario spans at most
 // (P + 7) / 32 + 1 of them
 constexpr int kMaxBlocks = (WM_MAX_OBSERVE_POINTS + 7 + kBlockPts - 1) / kBlockPts;   // 1025
-constexpr int kBlocksPerThread = (kMaxBlocks + kFastThreads - 1) / kFastThreads;   // 9
+constexpr int kBlocksPerThread = (kMaxBlocks + kFastThreads - 1) / kFastThreads;   // 5
 constexpr int kUbBins = 256;                                        // bound digit: 8 bins per octave
 constexpr int kUbShift = 20;
 constexpr uint32_t kUbLow = 114u << 3;                              // bin 0: keys below 2^-13
-constexpr int kUbPerThread = kUbBins / kFastThreads;                // 2
+constexpr int kUbPerThread = kUbBins / kFastThreads;                // 1
 constexpr int kWinBins = 1024;                                      // window digit: 128 bins per octave
 constexpr int kWinShift = 16;
-constexpr int kWinPerThread = kWinBins / kFastThreads;              // 8
+constexpr int kWinPerThread = kWinBins / kFastThreads;              // 4
 constexpr int kBndCap = 128;                                        // boundary-bin keys ranked directly
 constexpr int kBinRankCap = 128;                                    // keys of a lower bin ranked by counting
 constexpr int kPtsPerThread = 8;                                    // bounding pass: consecutive points per thread
@@ -546,6 +546,7 @@ constexpr int kGroupsPerPass = kFastThreads / kBlockPts;            // candidate
 constexpr int kBlockMinRows = 4;                                    // rows per ego for the block-pruned form
 constexpr int kScanRounds = 16;                                     // rounds loaded at once, keys kept
 constexpr int kRankPerThread = WM_MAX_TOPK / kFastThreads;          // keys below bin b per thread (c_less < 1024)
+static_assert(kUbPerThread >= 1 && kWinPerThread >= 2 && kRankPerThread >= 1, "at most 256 threads");
 
 // Block-wide exclusive prefix for kFastThreads threads (two barriers).
 __device__ __forceinline__ uint32_t fast_exclusive(uint32_t v, uint32_t *wtot, uint32_t *total)
@@ -617,8 +618,8 @@ __device__ __forceinline__ void write_row(const ObserveArgs &A, long out0, int r
     }
 }
 
-// three waves per SIMD: six work-groups per CU, as the LDS allows
-__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_observe_blocks(
+// four waves per SIMD: four work-groups of four waves per CU
+__global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_observe_blocks(
     ObserveArgs A, int rows, int row_chunk, int ego_chunk)
 {
     // work-group p: (scenario, ego range, row range); the XCD remap keeps a
