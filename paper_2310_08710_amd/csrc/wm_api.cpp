@@ -398,8 +398,10 @@ static int step_impl(const wm_batch *batch, const wm_state *cur, const wm_action
         tn.CW = 1;
         if (tn.G > 16)
             tn.G = 16;
-        if (!prepared)
+        if (!prepared) {
             wm::launch_compact_edges(*batch, *rg, w, L, st);
+            wm::launch_edge_boxes(*batch, w, L, st);
+        }
         wm::OffroadArgs o{batch->obj_off, batch->rg_off, *next, wm::ws_edges(w, L), m->offroad, m->offroad_margin,
                           nullptr, tn.G, tn.CW};
         wm::launch_offroad(*batch, o, st);
@@ -438,6 +440,7 @@ int wm_roadgraph_prepare(const wm_batch *batch, const wm_roadgraph *rg, void *ws
     const wm::WsLayout L = wm::ws_layout(batch->num_scenarios, batch->total_objects, batch->total_rg_points, 0, 0);
     CHECK(check_ws(ws, ws_bytes, L.total));
     wm::launch_compact_edges(*batch, *rg, (unsigned char *)ws, L, (hipStream_t)stream);
+    wm::launch_edge_boxes(*batch, (unsigned char *)ws, L, (hipStream_t)stream);
     return device_status("wm_roadgraph_prepare");
 }
 
@@ -534,6 +537,7 @@ int wm_offroad(const wm_batch *batch, const wm_state *st, const wm_roadgraph *rg
     hipStream_t s = (hipStream_t)stream;
     unsigned char *w = (unsigned char *)ws;
     wm::launch_compact_edges(*batch, *rg, w, L, s);
+    wm::launch_edge_boxes(*batch, w, L, s);
     wm::OffroadArgs o{batch->obj_off, batch->rg_off, *st, wm::ws_edges(w, L), offroad, margin, nearest_idx, tn.G,
                       tn.CW};
     {

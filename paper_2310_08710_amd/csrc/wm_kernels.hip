@@ -833,6 +833,52 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
     }
 }
 
+// A real road-edge point near (x, y), for a pruned scan with no nearest
+// point of a previous step: the block whose box has the nearest farthest
+// corner (among the chunks whose boxes may hold a point nearer than the best
+// chunk's farthest corner), and in it the nearest point of index < E.  Any
+// real point bounds the corner's nearest distance (scan_group_pruned); this
+// one is close to it.  (+inf, +inf) without edges.
+__device__ float2 seed_point(const float *__restrict__ stream, const float4 *cbox, const float4 *box, int E, float x,
+                             float y)
+{
+    const int nch = (E + kChunk - 1) / kChunk;
+    auto far_d2 = [&](const float4 b) {   // +inf for an empty box
+        const float fx = fabsf(b.x - x) > fabsf(b.y - x) ? b.x : b.y;
+        const float fy = fabsf(b.z - y) > fabsf(b.w - y) ? b.z : b.w;
+        return edge_d2(fx, fy, x, y);
+    };
+    float fc = __builtin_inff();
+    for (int c = 0; c < nch; ++c)
+        fc = fminf(fc, far_d2(cbox[c]));
+    float fb = __builtin_inff();
+    int bb = -1;
+    for (int c = 0; c < nch; ++c)
+        if (box_lb(cbox[c], x, y) <= fc)
+            for (int j = 0; j < 4; ++j) {
+                const float d = far_d2(box[4 * c + j]);
+                if (d < fb) {
+                    fb = d;
+                    bb = 4 * c + j;
+                }
+            }
+    float2 q = make_float2(__builtin_inff(), __builtin_inff());
+    if (bb < 0)
+        return q;
+    const float *col = stream + kChunkFloats * (bb >> 2) + 32 * (bb & 3);
+    const int n = min(32, E - 32 * bb);
+    float best = __builtin_inff();
+    for (int j = 0; j < n; ++j) {
+        const float px = col[j], py = col[kChunk + j];
+        const float d = edge_d2(px, py, x, y);
+        if (d < best) {
+            best = d;
+            q = make_float2(px, py);
+        }
+    }
+    return q;
+}
+
 // Spatial order of slice objects i0 .. i0+Ns-1: ascending by the Morton code
 // of their 8 m cell (invalid objects last), ties by index, into order[].
 // Neighbouring objects then share the groups of the pruned scan.  Two
@@ -1382,6 +1428,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (tid == 0)
             *gctr = 0;
         __syncthreads();
+        if (A.has_rg) {
+            // the first step's bounds: real points near the initial corners
+            for (int slot = tid; slot < 4 * Ns; slot += nthr) {
+                const int o = i0 + (slot >> 2);
+                float x, y;
+                box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+                prevq[slot] = seed_point(A.E.stream + 3 * eb, lds_boxes ? lcbox : A.E.cbox + eb / kChunk,
+                                         lds_boxes ? lbox : A.E.box + eb / kBoxPts, E, x, y);
+            }
+            __syncthreads();
+        }
         float my_loss = 0.f;
         for (int t = 1; t <= A.T; ++t) {
             const long row = (long)t * n, arow = (long)(t - 1) * n;
@@ -1477,6 +1534,78 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
+// The per-step off-road metric with the fused rollout's pruned scan (for
+// tunings of at most 512 threads): one work-group per (scenario, slice of 64
+// CW objects), each corner's scan bounded by a real point near it
+// (seed_point) instead of a previous step's nearest point.
+__global__ __launch_bounds__(512) void k_offroad_pruned(OffroadArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    ObjLds L;
+    const int U = 64 * A.CW, SL = 256 * A.CW, nthr = blockDim.x;
+    unsigned char *p = carve_objects(smem, U, L);
+    const ScanLds C = carve_scan_pruned(p, A.G, A.CW);
+    float *sk = (float *)(p + scan_pruned_lds_bytes(A.G, A.CW, 0));
+    int *nidx = (int *)(sk + SL);
+    float4 *lcbox = (float4 *)(nidx + SL);
+    float4 *lbox = lcbox + kLdsBoxChunks;
+    float2 *prevq = (float2 *)(lbox + 4 * kLdsBoxChunks);
+    uint32_t *okey = (uint32_t *)(prevq + 4 * U);
+    int *order = (int *)(okey + U);
+    int *gctr = order + U;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int o0 = __builtin_amdgcn_readfirstlane(A.obj_off[s]);
+    const int N = __builtin_amdgcn_readfirstlane(A.obj_off[s + 1]) - o0;
+    const int i0 = blockIdx.y * U;
+    if (i0 >= N)
+        return;
+    const int Ns = min(U, N - i0);
+    const long eb = edge_base(__builtin_amdgcn_readfirstlane(A.rg_off[s]), s);
+    // the count comes from the workspace, clamped to the scenario's capacity
+    const int E = __builtin_amdgcn_readfirstlane(max(0, min(A.E.count[s], A.rg_off[s + 1] - A.rg_off[s])));
+    const float qqmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.E.qqmax[s])));
+    const int nch = (E + kChunk - 1) / kChunk;
+    const bool lds_boxes = nch <= kLdsBoxChunks;
+    const float4 *gcbox = A.E.cbox + eb / kChunk, *gbox = A.E.box + eb / kBoxPts;
+    for (int i = tid; i < Ns; i += nthr)
+        load_object(L, i, A.st, o0 + i0 + i);
+    if (lds_boxes) {
+        for (int k = tid; k < nch; k += nthr)
+            lcbox[k] = gcbox[k];
+        for (int k = tid; k < 4 * nch; k += nthr)
+            lbox[k] = gbox[k];
+    }
+    if (tid == 0)
+        *gctr = 0;
+    __syncthreads();
+    const float4 *cbox = lds_boxes ? lcbox : gcbox, *box = lds_boxes ? lbox : gbox;
+    // each corner's bound: a real point near it
+    for (int slot = tid; slot < 4 * Ns; slot += nthr) {
+        const int o = slot >> 2;
+        float x, y;
+        box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
+        prevq[slot] = seed_point(A.E.stream + 3 * eb, cbox, box, E, x, y);
+    }
+    spatial_order(L, 0, Ns, okey, order);   // its first barrier orders prevq too
+    ScanCounts work{0u, 0u, 0u};
+    offroad_unit_pruned(L, 0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb, cbox, box, E, qqmax, C, sk,
+                        nidx, order, prevq, gctr, work);
+    __syncthreads();
+    for (int il = tid; il < Ns; il += nthr) {
+        float m = kNoValue;
+        for (int k = 0; k < 4; ++k)
+            m = fmaxf(m, sk[4 * il + k]);
+        const long g = o0 + i0 + il;
+        if (A.offroad)
+            A.offroad[g] = (uint8_t)(m > 0.f);
+        if (A.margin)
+            A.margin[g] = m;
+        if (A.nearest)
+            for (int k = 0; k < 4; ++k)
+                A.nearest[4 * g + k] = nidx[4 * il + k];
+    }
+}
+
 __global__ void k_loss_reduce(int S, const int32_t *__restrict__ uoff, const float *__restrict__ lossp,
                               float *__restrict__ loss)
 {
@@ -1547,8 +1676,19 @@ static size_t offroad_scratch(int G, int CW) { return scan_lds_bytes(G, CW) + (s
 
 void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
 {
-    const size_t lds = objects_lds(64 * a.CW) + offroad_scratch(a.G, a.CW);
     const int slices = (b.max_objects + 64 * a.CW - 1) / (64 * a.CW);
+    if (64 * a.CW * a.G <= 512) {
+        // the pruned scan: objects, scan region, results, boxes, bounds,
+        // keys, order and the group counter
+        const size_t lds = objects_lds(64 * a.CW) + scan_pruned_lds_bytes(a.G, a.CW, 0) + (size_t)256 * a.CW * 8 +
+                           (size_t)kLdsBoxChunks * 80 + (size_t)64 * a.CW * 40 + 16;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_offroad_pruned, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+        hipLaunchKernelGGL(k_offroad_pruned, dim3(b.num_scenarios, slices), dim3(64 * a.CW * a.G), lds, st, a);
+        return;
+    }
+    const size_t lds = objects_lds(64 * a.CW) + offroad_scratch(a.G, a.CW);
     if (lds > 65536)
         // a failure here makes the launch below fail, which the caller reports
         (void)hipFuncSetAttribute((const void *)k_offroad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
