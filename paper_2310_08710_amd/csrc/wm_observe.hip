@@ -503,7 +503,8 @@ __device__ __forceinline__ void observe_exact_item(const ObserveArgs &A, int row
 // so 32 consecutive points (a block) span a short stretch of road.  A
 // work-group takes one scenario, a range of state rows and a range of egos;
 // it first bounds every block (box of its valid points, rounded outwards to
-// half precision, and the valid count) in LDS, then for each (row, ego):
+// half precision, the valid count and a bit mask of the valid points) in
+// LDS, then for each (row, ego):
 //   1. lb / ub = binary32 key of the nearest / farthest point of the box;
 //      rounding is monotone, so lb <= key <= ub for every valid point of the
 //      block.  The histogram of ub weighted by the valid counts gives a bound
@@ -519,7 +520,7 @@ __device__ __forceinline__ void observe_exact_item(const ObserveArgs &A, int row
 // Egos whose bin b holds more than kBndCap keys, or a lower bin more than
 // kBinRankCap (many equal or nearly equal keys), are handed to the exact
 // kernel above: their first rg_idx place is set to kHandOver and nothing else
-// is written for them here.  Work-groups are small (four waves, 26 KB of LDS)
+// is written for them here.  Work-groups are small (four waves, 30 KB of LDS)
 // so that four of them, each with its own ego, share a CU.
 // ---------------------------------------------------------------------------
 constexpr int kFastThreads = 256;
@@ -636,6 +637,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
 
     __shared__ uint2 bbox[kMaxBlocks];           // half-precision (xmin, xmax), (ymin, ymax) of the valid points
     __shared__ uint8_t bcnt[kMaxBlocks];         // valid points of the block
+    __shared__ uint32_t bmask[kMaxBlocks];       // bit i: point 32 b + i - lead is in the scenario and valid
     __shared__ uint32_t ubh[kUbBins];            // ub histogram weighted by valid counts
     __shared__ uint32_t whist[kWinBins / 2];     // window histogram, then the scatter cursors: 16-bit
                                                  // counters, bin b in word b % 512, half b / 512
@@ -702,8 +704,10 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
             const int t0 = c0 + gq * kBoundChunk + kPtsPerThread * tid;
             float xmn = __builtin_inff(), xmx = -__builtin_inff(), ymn = __builtin_inff(), ymx = -__builtin_inff();
             int cnt = 0;
+            uint32_t bits = 0;
 #pragma unroll
             for (int i = 0; i < kPtsPerThread; ++i) {
+                bits |= (pv[gq][i] ? 1u : 0u) << i;
                 if (pv[gq][i]) {
                     xmn = fminf(xmn, px[gq][i]);
                     xmx = fmaxf(xmx, px[gq][i]);
@@ -720,10 +724,14 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                 ymx = fmaxf(ymx, __shfl_xor(ymx, d));
                 cnt += __shfl_xor(cnt, d);
             }
+            bits <<= kPtsPerThread * (tid & 3);
+            bits |= __shfl_xor(bits, 1);
+            bits |= __shfl_xor(bits, 2);
             const int blk = t0 / kBlockPts;
             if ((tid & 3) == 0 && blk < NB) {
                 bbox[blk] = make_uint2(pack_down_up(xmn, xmx), pack_down_up(ymn, ymx));
                 bcnt[blk] = (uint8_t)cnt;
+                bmask[blk] = bits;
                 nvalid_local += cnt;
             }
         }
@@ -801,6 +809,10 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                     const int j = c < NC ? kBlockPts * (int)cblk[c] + bl - lead : -1;
                     return j < P ? j : -1;
                 };
+                auto valid_of = [&](int r) {   // the point of round r is valid
+                    const int c = cb + kGroupsPerPass * r;
+                    return c < NC && ((bmask[cblk[c]] >> bl) & 1u) != 0;
+                };
                 auto load_keys = [&](int rb) {
                     float qx[kScanRounds], qy[kScanRounds];
                     bool qv[kScanRounds];
@@ -809,11 +821,10 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                         qv[q] = false;
                         qx[q] = qy[q] = 0.f;
                         if (rb + q < R) {   // work-group uniform
-                            const int j = point_of(rb + q);
-                            const int jj = max(j, 0);
+                            const int jj = max(point_of(rb + q), 0);
                             qx[q] = rx[jj];
                             qy[q] = ry[jj];
-                            qv[q] = j >= 0 && rv[jj] != 0;
+                            qv[q] = valid_of(rb + q);
                         }
                     }
 #pragma unroll
@@ -909,7 +920,7 @@ __global__ __launch_bounds__(kFastThreads) __attribute__((amdgpu_waves_per_eu(4)
                     NC = __builtin_amdgcn_readfirstlane(sh[1]);
                     const uint32_t dU = (U - 1u) >> kWinShift;
                     dlo = dU > (uint32_t)(kWinBins - 1) ? dU - (uint32_t)(kWinBins - 1) : 0u;
-                    // candidate c of round r is block cblk[c], c = tid / 32 + 4 r;
+                    // candidate c of round r is block cblk[c], c = tid / 32 + 8 r;
                     // kScanRounds rounds are loaded at once and their keys kept
                     R = (NC + kGroupsPerPass - 1) / kGroupsPerPass;
 

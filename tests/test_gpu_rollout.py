@@ -589,3 +589,42 @@ def test_autotune_cache_file(tmp_path, monkeypatch):
     path.write_text("wm-tune 3 %s %d %d %d %d\n" % (tag, ob, pb, planted[0], planted[1]))
     assert tuple(wm.autotune(ds.batch, ds.init, ds.act_seq, ds.log_seq, ds.rg, T, sc.dt, ws)) == planted
     assert len(path.read_text().splitlines()) == 1   # taken, not timed and appended
+
+
+def test_pruned_scans_with_boxes_in_global_memory():
+    """Scenarios of 55,000-60,000 road points (about 37,000 road-edge points,
+    more than 256 chunks of 128): the pruned scans then read the chunk and
+    block boxes from global memory instead of LDS.  The per-step off-road
+    with the pruned scan (tuning 64 x 8) equals the scan of every point
+    (tuning 256 x 4, 1024 threads) bit for bit and agrees with the oracle;
+    the fused rollout equals the plain steps bit for bit."""
+    import torch
+    from paper_2310_08710_amd import wm
+    dev = device()
+    sc = synth.make_scene(4, scenarios=2, objects=(20, 70), rg_points=(55000, 60000), steps=3,
+                          rg_invalid_frac=0.02, object_box=40, on_road_frac=0.5)
+    edges = [int(((sc.rg["type"][a:b] == synth.TYPE_ROAD_EDGE) & (sc.rg["valid"][a:b] != 0)).sum())
+             for a, b in zip(sc.rg_off[:-1], sc.rg_off[1:])]
+    assert min(edges) > 256 * 128, edges
+    ds = wm.upload(sc, dev)
+    n = sc.total_objects
+    ws = ds.batch.workspace()
+    res = {}
+    for tune in ((64, 8), (256, 4)):
+        off = torch.empty(n, dtype=torch.uint8, device=dev)
+        mg = torch.empty(n, device=dev)
+        near = torch.empty((n, 4), dtype=torch.int32, device=dev)
+        wm.offroad(ds.batch, ds.init, ds.rg, ws, off, mg, near, tune=tune)
+        torch.cuda.synchronize()
+        res[tune] = (off, mg, near)
+    for a, b in zip(res[(64, 8)], res[(256, 4)]):
+        assert torch.equal(a, b)
+    ref = oracle.offroad(sc.obj_off, sc.rg_off, f64(sc.state_at(synth.T0)), f64(sc.rg))
+    off, mg, _ = res[(64, 8)]
+    ties = compare_offroad(off.cpu().numpy(), mg.cpu().numpy(), ref, "global boxes")
+    assert ties <= n // 20
+    traj, met, _, _ = _run_fused(ds, sc, dev)
+    ptraj, pmet = _run_plain(ds, sc, dev)
+    assert torch.equal(traj.x, ptraj.x)
+    for f in ("offroad", "offroad_margin", "collision", "overlap_margin"):
+        assert torch.equal(getattr(met, f), getattr(pmet, f)), f
