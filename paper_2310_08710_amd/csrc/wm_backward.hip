@@ -23,7 +23,8 @@
 //      fixed shuffle tree.  A lane first marks the partners close enough for
 //      a non-zero term (a distance bound); the wave evaluates its marked pairs
 //      one per lane, and each lane adds its own terms in ascending partner
-//      order.
+//      order.  It also writes the zero gradients of the block's steps for
+//      the objects that are not differentiated.
 //   C. k_bwd_reverse, one work-group per scenario, one thread per
 //      controlled object: the reverse recursion over all T steps, the
 //      log-divergence term 2 (p - p_log) and the pair terms added, then back
@@ -45,7 +46,7 @@ constexpr float kCullGap = 9.0f;
 static_assert(kCullGap / kSoftScale * 1.4426950f > 129.0f, "skipped terms overflow the exponential");
 static_assert(WM_MAX_OBJECTS <= 64 * 32, "a lane's partners fit in one 32-bit mask");
 
-constexpr int kRecThreads = 256;
+constexpr int kRecThreads = 64;
 constexpr int kRecBatch = 8;     // recomputed steps whose inputs are loaded together
 constexpr int kPairThreads = 512;
 constexpr int kRevThreads = 256;
@@ -99,32 +100,17 @@ __device__ __forceinline__ int live_objects(const BackwardArgs &A, int o0, int N
 
 // A. ------------------------------------------------------------------------
 // One work-group per (scenario, checkpoint segment), one thread per
-// controlled object: the segment is recomputed from its checkpoint; the
-// gradients of the objects that are not differentiated are zeroed.
+// controlled object: the segment is recomputed from its checkpoint.
 __global__ __launch_bounds__(kRecThreads) void k_bwd_recompute(BackwardArgs A)
 {
     __shared__ int cidx[WM_MAX_OBJECTS];
     __shared__ int wcnt[kRecThreads / 64];
-    __shared__ uint8_t live[WM_MAX_OBJECTS];
     const int nseg = (A.T + A.K - 1) / A.K;
     const int s = blockIdx.x / nseg, c = blockIdx.x - s * nseg;
     const int t0 = c * A.K, t1 = min(A.T, t0 + A.K);
     const int o0 = A.obj_off[s], N = A.obj_off[s + 1] - o0;
     const long n = A.n;
     const int NC = live_objects(A, o0, N, cidx, wcnt);
-    for (int i = threadIdx.x; i < N; i += kRecThreads)
-        live[i] = 0;
-    __syncthreads();
-    for (int q = threadIdx.x; q < NC; q += kRecThreads)
-        live[cidx[q]] = 1;
-    __syncthreads();
-    // not differentiated: zero gradients (of this segment's steps)
-    for (int t = t0; t < t1; ++t)
-        for (int i = threadIdx.x; i < N; i += kRecThreads)
-            if (!live[i]) {
-                A.grad_a[(long)t * n + o0 + i] = 0.f;
-                A.grad_k[(long)t * n + o0 + i] = 0.f;
-            }
     const float dt = A.dt, hdt2 = 0.5f * dt * dt;
     for (int q = threadIdx.x; q < NC; q += kRecThreads) {
         const long g = o0 + cidx[q];
@@ -197,6 +183,16 @@ __global__ __launch_bounds__(kPairThreads) void k_bwd_pairs(BackwardArgs A)
 
     // each object's kind; the controlled, valid objects in index order
     const int NC = live_objects(A, o0, N, cidx, wcnt, kind);
+    // the objects that are not differentiated get zero gradients at the
+    // block's steps (actions tb_lo .. tb_lo + nb - 1)
+    for (int it = tid; it < nb * N; it += nthr) {
+        const int tb = it / N, i = it - tb * N;
+        if (kind[i] != 2) {
+            const long at = (long)(tb_lo + tb) * n + o0 + i;
+            A.grad_a[at] = 0.f;
+            A.grad_k[at] = 0.f;
+        }
+    }
     if (NC == 0)
         return;   // work-group uniform
     // partner split: G lanes (a power of two <= 64) per (step, controlled
