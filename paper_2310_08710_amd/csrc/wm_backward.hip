@@ -51,7 +51,7 @@ constexpr int kRecBatch = 8;     // recomputed steps whose inputs are loaded tog
 constexpr int kPairThreads = 512;
 constexpr int kRevThreads = 256;
 constexpr size_t kPairStepBytes = 16 + 8;        // LDS per step and object in k_bwd_pairs
-constexpr size_t kPairStageBudget = 30 * 1024;
+constexpr size_t kPairStageBudget = 24 * 1024;
 constexpr int kPairMaxSteps = 16;
 constexpr int kPairBatch = 4;    // staged (step, object) items per thread with loads in flight together
 
@@ -411,6 +411,7 @@ __device__ __forceinline__ void rev_step(const BackwardArgs &A, const RevStep &c
 // previous chunk from LDS.
 constexpr int kRevStage = 24576;
 constexpr int kRevF4 = 5;   // float4 per (step, object): pair sums + 4 of the record
+constexpr int kRevBatch = 8;
 
 __global__ __launch_bounds__(kRevThreads) void k_bwd_reverse(BackwardArgs A)
 {
@@ -431,14 +432,24 @@ __global__ __launch_bounds__(kRevThreads) void k_bwd_reverse(BackwardArgs A)
         const long n = A.n;
         // chunk c holds steps t = T - c C down to max(1, T - (c + 1) C + 1):
         // element (u, q, r) at ((u * NC + q) * kRevF4 + r) of its buffer
+        // (kRevBatch loads of a thread in flight together)
         auto stage_chunk = [&](int c, int first, int stride) {
             float4 *buf = rstage + (long)(c & 1) * (kRevStage / 16);
             const int thi = T - c * C, nstep = min(C, thi);
             const int items = nstep * NC * kRevF4;
-            for (int e = first; e < items; e += stride) {
-                const int r = e % kRevF4, uq = e / kRevF4, q = uq % NC, u = uq / NC;
-                const long at = (long)(thi - u - 1) * n + o0 + cidx[q];
-                buf[e] = r == 0 ? ((const float4 *)A.part)[at] : ((const float4 *)A.rec)[4 * at + (r - 1)];
+            for (int e0 = first; e0 < items; e0 += kRevBatch * stride) {
+                float4 v[kRevBatch];
+#pragma unroll
+                for (int b = 0; b < kRevBatch; ++b) {
+                    const int e = min(e0 + b * stride, items - 1);
+                    const int r = e % kRevF4, uq = e / kRevF4, q = uq % NC, u = uq / NC;
+                    const long at = (long)(thi - u - 1) * n + o0 + cidx[q];
+                    v[b] = r == 0 ? ((const float4 *)A.part)[at] : ((const float4 *)A.rec)[4 * at + (r - 1)];
+                }
+#pragma unroll
+                for (int b = 0; b < kRevBatch; ++b)
+                    if (e0 + b * stride < items)
+                        buf[e0 + b * stride] = v[b];
             }
         };
         stage_chunk(0, threadIdx.x, kRevThreads);
