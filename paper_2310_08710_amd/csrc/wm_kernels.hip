@@ -622,14 +622,21 @@ __device__ void offroad_unit(const ObjLds &L, int i0, int Ns, const float *__res
 // claim groups from the counter *gctr (zero at entry) until none is left.
 // prevq[slot] (slot = 4 il + corner) is the corner's nearest road-edge point
 // of the previous step ((+inf, +inf): none), whose distance bounds what the
-// scan must look at (scan_group_pruned).  Writes the candidate arrays of C
-// (one split) for every slot of the slice.
+// scan must look at (scan_group_pruned).  Right after a group's scan its
+// wave settles each corner: the best block and a second one within the
+// band of it are rescanned exactly (four lanes per corner, the lanes that
+// held the corner in the scan), and sk, nidx and prevq of the slot written;
+// a corner with three or more blocks within the band is appended to C.full
+// with the exact scan's bound in C.b3 (its sk, nidx and prevq are left to
+// that scan).  *C.nfull must be zero at entry.
 template <int GO>
 __device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
+                               const float2 *__restrict__ edir, const int32_t *__restrict__ eidx,
                                const float4 *cbox, const float4 *box, int E, float qqmax, const ScanLds &C,
-                               const int *order, const float2 *prevq, int *gctr, ScanCounts &work)
+                               const int *order, float2 *prevq, float *sk, int *nidx, int *gctr, ScanCounts &work)
 {
     constexpr int CL = 16 / GO;   // lanes per corner
+    static_assert(CL == kBlockRescanLanes, "a corner's scan lanes rescan its candidate blocks");
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nch = (E + kChunk - 1) / kChunk;
@@ -659,96 +666,30 @@ __device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__r
         const float orad = 0.5f * sqrtf(__builtin_fmaf(L.wid[o], L.wid[o], L.len[o] * L.len[o]));
         scan_group_pruned<GO>(stream, cbox, box, nch, stage, list, cx, cy, thr, L.x[o], L.y[o], orad, b1, b2, b3,
                               i1, i2, work);
-        if (il >= 0 && lane % CL == 0) {
-            const int at = 4 * il + (k & 3);
-            C.b1[at] = b1;
-            C.b2[at] = b2;
-            C.b3[at] = b3;
-            C.i1[at] = i1;
-            C.i2[at] = i2;
-        }
-    }
-}
-
-// The fused rollout's off-road step for slice objects i0 .. i0+Ns-1 (the
-// result of offroad_unit, with the scan pruned: offroad_groups).  prevq
-// receives this step's nearest points.  *gctr must be zero at entry; it is
-// zero again at return.
-__device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, const float *__restrict__ stream,
-                                    const float2 *__restrict__ edir, const int32_t *__restrict__ eidx,
-                                    const float4 *cbox, const float4 *box, int E, float qqmax, ScanLds C, float *sk,
-                                    int *nidx, const int *order, float2 *prevq, int *gctr, ScanCounts &work)
-{
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int splits = 1;
-    const int SL = 4 * U;
-    const int nslots = 4 * Ns;
-    if (tid == 0)
-        *C.nfull = 0;
-    offroad_groups<kGroupObjects>(L, i0, Ns, stream, cbox, box, E, qqmax, C, order, prevq, gctr, work);
-    __syncthreads();
-    if (tid == 0)
-        *gctr = 0;
-    for (int slot = tid; slot < nslots; slot += blockDim.x) {
-        // best block (one split)
-        float b = __builtin_inff();
-        int bc = -1;
-        for (int h = 0; h < splits; ++h) {
-            const float v = C.b1[h * SL + slot];
-            if (v < b) {
-                b = v;
-                bc = C.i1[h * SL + slot];
-            }
-        }
-        const int o = i0 + (slot >> 2);
-        int lo = -1, hi = -1;   // candidate blocks; lo: -1 none, -2 the exact scan of every point
-        if (bc >= 0 && L.valid[o]) {
-            float x, y;
-            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
-            const float lim = b + candidate_band(qqmax, x, y);
-            int other = -1;        // a second candidate block
-            bool full = false;     // three or more candidates: exact scan of every point
-            for (int h = 0; h < splits; ++h) {
-                const int at = h * SL + slot;
-                if (C.b3[at] <= lim)
-                    full = true;
-                const int cand[2] = {C.i1[at], C.i2[at]};
-                const float val[2] = {C.b1[at], C.b2[at]};
-                for (int q = 0; q < 2; ++q) {
-                    if (val[q] <= lim && cand[q] != bc && cand[q] != other) {
-                        if (other < 0)
-                            other = cand[q];
-                        else
-                            full = true;
-                    }
-                }
-            }
-            if (full) {
-                C.full[atomicAdd(C.nfull, 1)] = slot;
-                // the exact scan's bound on D (b is a minimum of T = D - |c|^2)
-                C.b3[slot] = (b + __builtin_fmaf(y, y, x * x)) + candidate_band(qqmax, x, y);
+        // candidate blocks: lo -1 none, -2 the exact scan of every block
+        const int part = lane % CL, slot = 4 * il + (k & 3);
+        int lo = -1, hi = -1;
+        if (il >= 0 && i1 >= 0 && L.valid[o]) {
+            const float lim = b1 + candidate_band(qqmax, cx, cy);
+            if (b3 <= lim) {
                 lo = -2;
+                if (part == 0) {
+                    C.full[atomicAdd(C.nfull, 1)] = slot;
+                    // the exact scan's bound on D (b1 is a minimum of T = D - |c|^2)
+                    C.b3[slot] = (b1 + __builtin_fmaf(cy, cy, cx * cx)) + candidate_band(qqmax, cx, cy);
+                }
             } else {
-                lo = other >= 0 ? min(bc, other) : bc;
-                hi = other >= 0 ? max(bc, other) : -1;
+                const int other = b2 <= lim && i2 != i1 ? i2 : -1;
+                lo = other >= 0 ? min(i1, other) : i1;
+                hi = other >= 0 ? max(i1, other) : -1;
             }
         }
-        nidx[slot] = lo;
-        sk[slot] = __int_as_float(hi);
-    }
-    __syncthreads();
-    for (int u0 = 0; u0 < nslots * kBlockRescanLanes; u0 += blockDim.x) {   // block-uniform trip count
-        const int u = u0 + tid, slot = u / kBlockRescanLanes, rl = u % kBlockRescanLanes;
-        const bool act = slot < nslots;
-        const int lo = act ? nidx[slot] : -1, hi = act ? __float_as_int(sk[slot]) : -1;
-        float best = __builtin_inff(), x = 0.f, y = 0.f;
+        float best = __builtin_inff();
         int bj = 0x7fffffff;
         if (lo >= 0) {
-            const int o = i0 + (slot >> 2);
-            box_corner(L.x[o], L.y[o], L.c[o], L.s[o], 0.5f * L.len[o], 0.5f * L.wid[o], slot & 3, x, y);
-            rescan_block(stream, lo, rl, E, x, y, best, bj);
+            rescan_block(stream, lo, part, E, cx, cy, best, bj);
             if (hi >= 0)
-                rescan_block(stream, hi, rl, E, x, y, best, bj);
+                rescan_block(stream, hi, part, E, cx, cy, best, bj);
         }
         for (int off = kBlockRescanLanes / 2; off > 0; off >>= 1) {
             const float ob = __shfl_xor(best, off);
@@ -758,7 +699,7 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
                 bj = oj;
             }
         }
-        if (act && rl == 0) {
+        if (il >= 0 && part == 0) {
             float s_val = kNoValue;
             int near = -1;
             float2 pq = make_float2(__builtin_inff(), __builtin_inff());
@@ -766,7 +707,7 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
                 const float *ch = stream + kChunkFloats * (bj / kChunk) + (bj % kChunk);
                 const float qx = ch[0], qy = ch[kChunk];
                 const float2 d = edir[bj];
-                s_val = -__builtin_fmaf(d.x, y - qy, -(d.y * (x - qx)));
+                s_val = -__builtin_fmaf(d.x, cy - qy, -(d.y * (cx - qx)));
                 near = eidx[bj];
                 pq = make_float2(qx, qy);
             }
@@ -776,7 +717,27 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, cons
             nidx[slot] = near;
         }
     }
+}
+
+// The fused rollout's off-road step for slice objects i0 .. i0+Ns-1 (the
+// result of offroad_unit, with the scan pruned: offroad_groups).  prevq
+// receives this step's nearest points.  *gctr must be zero at entry; it is
+// zero again at return.  *C.nfull must be zero at entry, set so before a
+// barrier that precedes the call (the corners of the exact scan are
+// counted during the groups); the caller clears it again before the next
+// call, after every thread has passed this call.
+__device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, const float *__restrict__ stream,
+                                    const float2 *__restrict__ edir, const int32_t *__restrict__ eidx,
+                                    const float4 *cbox, const float4 *box, int E, float qqmax, ScanLds C, float *sk,
+                                    int *nidx, const int *order, float2 *prevq, int *gctr, ScanCounts &work)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    (void)U;
+    offroad_groups<kGroupObjects>(L, i0, Ns, stream, edir, eidx, cbox, box, E, qqmax, C, order, prevq, sk, nidx,
+                                  gctr, work);
     __syncthreads();
+    if (tid == 0)
+        *gctr = 0;
     const int nf = *C.nfull;
     const int nthr = blockDim.x, nw = nthr >> 6, w = tid >> 6;
     for (int f = 0; f < nf; ++f) {
@@ -1484,6 +1445,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
             overlap_partial(L, N, i0, Ns, U, P, red, A.want_loss ? &my_loss : nullptr, nullptr, nullptr);
             if (A.has_rg) {
+                if (tid == 0)
+                    *C.nfull = 0;   // every thread has read the last step's count (barriers since)
                 spatial_order(L, i0, Ns, okey, order);
                 offroad_unit_pruned(L, i0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb,
                                     lds_boxes ? lcbox : A.E.cbox + eb / kChunk,
@@ -1575,8 +1538,10 @@ __global__ __launch_bounds__(512) void k_offroad_pruned(OffroadArgs A)
         for (int k = tid; k < 4 * nch; k += nthr)
             lbox[k] = gbox[k];
     }
-    if (tid == 0)
+    if (tid == 0) {
         *gctr = 0;
+        *C.nfull = 0;
+    }
     __syncthreads();
     const float4 *cbox = lds_boxes ? lcbox : gcbox, *box = lds_boxes ? lbox : gbox;
     // each corner's bound: a real point near it
