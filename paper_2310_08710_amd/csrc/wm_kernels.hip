@@ -363,6 +363,8 @@ constexpr int kGroupObjects = 4;
 // the fused rollout copies into LDS; a scenario with more reads them from
 // global memory.
 constexpr int kLdsBoxChunks = 256;
+// Steps between renewals of the fused rollout's spatial order.
+constexpr int kReorderSteps = 4;
 
 // LDS of the pruned scan: per wave kPruneWaveBytes, the five candidate
 // arrays of SL = 256 CW corner slots, the slots of the exact scan, then two
@@ -1447,7 +1449,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (A.has_rg) {
                 if (tid == 0)
                     *C.nfull = 0;   // every thread has read the last step's count (barriers since)
-                spatial_order(L, i0, Ns, okey, order);
+                // objects move little in a step: the spatial order is renewed
+                // every kReorderSteps steps (it only shapes the groups; every
+                // corner's result is exact whatever the groups)
+                if ((t - 1) % kReorderSteps == 0)
+                    spatial_order(L, i0, Ns, okey, order);
+                else
+                    __syncthreads();
                 offroad_unit_pruned(L, i0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb,
                                     lds_boxes ? lcbox : A.E.cbox + eb / kChunk,
                                     lds_boxes ? lbox : A.E.box + eb / kBoxPts, E, qqmax, C, sk, nidx, order, prevq,
