@@ -434,8 +434,12 @@ template <int Ctrl>
 __device__ __forceinline__ float dpp_min(float v)
 {
     // every lane's source lane exists in these patterns, so bound_ctrl
-    // changes nothing but spares the move of a default value
-    return fminf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Ctrl, 0xF, 0xF, true)));
+    // changes nothing but spares the move of a default value; the median
+    // with -FLT_MAX is the minimum of two values above it in one
+    // instruction (fminf would first quiet the moved value, which is never
+    // a NaN here)
+    return __builtin_amdgcn_fmed3f(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), Ctrl, 0xF, 0xF, true)),
+                                   -0x1.fffffep127f);
 }
 
 template <int CL>
