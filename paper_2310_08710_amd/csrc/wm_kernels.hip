@@ -400,10 +400,12 @@ constexpr int kReorderSteps = 4;
 // its overlap (32 bytes of LDS per object).
 constexpr int kPackedMaxN = 256;
 
-// LDS of the pruned scan: per wave kPruneWaveBytes, the five candidate
-// arrays of SL = 256 CW corner slots, the slots of the exact scan, then two
-// counters (exact-scan slots, claimed groups); a region of at least
-// `floor` bytes (the IDM lead search shares it).
+// LDS of the pruned scan: per wave kPruneWaveBytes, five arrays of SL = 256
+// CW corner slots (of which the pruned path uses b3, the exact scan's bound
+// per slot, and the first entries of b1 and i1, the waves' minima in that
+// scan), the slots of the exact scan, then two counters (exact-scan slots,
+// claimed groups); a region of at least `floor` bytes (the IDM lead search
+// shares it).
 __device__ __forceinline__ ScanLds carve_scan_pruned(void *p, int G, int CW)
 {
     float4 *stage = (float4 *)p;
