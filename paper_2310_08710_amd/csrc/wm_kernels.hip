@@ -764,13 +764,12 @@ __device__ void offroad_groups(const ObjLds &L, int i0, int Ns, const float *__r
 // barrier that precedes the call (the corners of the exact scan are
 // counted during the groups); the caller clears it again before the next
 // call, after every thread has passed this call.
-__device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, int U, const float *__restrict__ stream,
+__device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, const float *__restrict__ stream,
                                     const float2 *__restrict__ edir, const int32_t *__restrict__ eidx,
                                     const float4 *cbox, const float4 *box, int E, float qqmax, ScanLds C, float *sk,
                                     int *nidx, const int *order, float2 *prevq, int *gctr, ScanCounts &work)
 {
     const int tid = threadIdx.x, lane = tid & 63;
-    (void)U;
     offroad_groups<kGroupObjects>(L, i0, Ns, stream, edir, eidx, cbox, box, E, qqmax, C, order, prevq, sk, nidx,
                                   gctr, work);
     __syncthreads();
@@ -1502,7 +1501,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                     spatial_order(L, i0, Ns, okey, order);
                 else
                     __syncthreads();
-                offroad_unit_pruned(L, i0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb,
+                offroad_unit_pruned(L, i0, Ns, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb,
                                     lds_boxes ? lcbox : A.E.cbox + eb / kChunk,
                                     lds_boxes ? lbox : A.E.box + eb / kBoxPts, E, qqmax, C, sk, nidx, order, prevq,
                                     gctr, work);
@@ -1607,7 +1606,7 @@ __global__ __launch_bounds__(512) void k_offroad_pruned(OffroadArgs A)
     }
     spatial_order(L, 0, Ns, okey, order);   // its first barrier orders prevq too
     ScanCounts work{0u, 0u, 0u};
-    offroad_unit_pruned(L, 0, Ns, U, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb, cbox, box, E, qqmax, C, sk,
+    offroad_unit_pruned(L, 0, Ns, A.E.stream + 3 * eb, A.E.dir + eb, A.E.idx + eb, cbox, box, E, qqmax, C, sk,
                         nidx, order, prevq, gctr, work);
     __syncthreads();
     for (int il = tid; il < Ns; il += nthr) {
