@@ -178,6 +178,32 @@ __device__ __forceinline__ int idm_segment(Wf w, int T, float s)
     return lo;
 }
 
+// idm_segment of arc lengths w(k) = path[k].w for an s whose segment is
+// known to be at least lo0 (every row k < lo0 has w(k) <= s, e.g. the
+// segment of an earlier, smaller arc length): the next four rows are loaded
+// at once, the rest searched by bisection.  The same index as idm_segment.
+__device__ __forceinline__ int idm_segment_from(const float4 *__restrict__ path, int T, float s, int lo0)
+{
+    lo0 = max(lo0, 1);
+    float w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        w[j] = path[min(lo0 + j, T)].w;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (lo0 + j <= T && w[j] > s)
+            return lo0 + j;
+    int lo = min(lo0 + 4, T + 1), hi = T + 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (path[mid].w > s)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
 // The pose at arc length s given its segment lo (idm_segment): linear
 // between path points lo - 1 and lo, the last point past the end.
 __device__ __forceinline__ void idm_interp(const float4 *__restrict__ path, int T, int lo, float s, float &x, float &y,
@@ -195,12 +221,6 @@ __device__ __forceinline__ void idm_interp(const float4 *__restrict__ path, int 
     x = __builtin_fmaf(lam, b.x - a.x, a.x);
     y = __builtin_fmaf(lam, b.y - a.y, a.y);
     yaw = __builtin_fmaf(lam, wrap_angle(b.z - a.z), a.z);
-}
-
-__device__ __forceinline__ void idm_pose(const float4 *__restrict__ path, int T, float s, float &x, float &y,
-                                         float &yaw)
-{
-    idm_interp(path, T, idm_segment([&](int k) { return path[k].w; }, T, s), s, x, y, yaw);
 }
 
 // IDM acceleration for speed v; `lead` selects the interaction term with gap

@@ -1154,13 +1154,9 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
     const bool use_mask = A.maxN <= kIdmMaskMaxN;
     const int W = (N + 31) >> 5;
     float *rad = ia;   // circumradius per object, until the accelerations are written
-    for (int i = tid; i < N; i += nthr) {
+    // (pc holds each agent's pose at sig, kept by idm_move)
+    for (int i = tid; i < N; i += nthr)
         rad[i] = 0.5f * sqrtf(__builtin_fmaf(L.wid[i], L.wid[i], L.len[i] * L.len[i]));
-        if (use_mask && agent[i]) {
-            float yaw;
-            idm_pose(A.idmP + (long)(o0 + i) * (A.T + 1), A.T, sig[i], pc[2 * i], pc[2 * i + 1], yaw);
-        }
-    }
     __syncthreads();
     const float reach = (float)M * A.idm.lookahead_step;
     if (use_mask) {
@@ -1282,9 +1278,11 @@ __device__ __forceinline__ void idm_leads(const RollArgs &A, const ObjLds &L, in
 }
 
 // Advance IDM agent i (global g) with acceleration a along its path; the
-// next state's length, width and valid come from log row `row`.
+// next state's length, width and valid come from log row `row`.  sg[i] is
+// the path segment of sig[i] (progress never decreases, so the new segment
+// is searched from it); pc receives the new pose's position.
 __device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int i, long g, long row, float *sig,
-                                         float a)
+                                         int *sg, float *pc, float a)
 {
     const float dt = A.dt;
     const float v = sqrtf(__builtin_fmaf(L.vy[i], L.vy[i], L.vx[i] * L.vx[i]));
@@ -1304,7 +1302,11 @@ __device__ __forceinline__ void idm_move(const RollArgs &A, const ObjLds &L, int
         sig[i] += adv;
     }
     float x, y, yaw, sn, cs;
-    idm_pose(path, A.T, sig[i], x, y, yaw);
+    const int lo = idm_segment_from(path, A.T, sig[i], sg[i]);
+    sg[i] = lo;
+    idm_interp(path, A.T, lo, sig[i], x, y, yaw);
+    pc[2 * i] = x;
+    pc[2 * i + 1] = y;
     sincosf(yaw, &sn, &cs);
     L.x[i] = x;
     L.y[i] = y;
@@ -1360,7 +1362,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     int *lk = (int *)(ia + A.maxN);      // IDM: lead key m * 2048 + j
     uint8_t *agent = (uint8_t *)(lk + A.maxN);
     float *pc = (float *)(agent + align_up((size_t)A.maxN, 16));   // IDM: pose at sig (x, y)
-    uint32_t *mask = (uint32_t *)(pc + 2 * A.maxN);                   // IDM: candidate bit masks
+    int *sg = (int *)(pc + 2 * A.maxN);                               // IDM: path segment of sig
+    uint32_t *mask = (uint32_t *)(sg + A.maxN);                       // IDM: candidate bit masks
     // the pruned off-road scan: the scenario's chunk and block boxes (when at
     // most kLdsBoxChunks chunks), each corner's nearest road-edge point of the
     // previous step, spatial keys and order of the slice's objects, the
@@ -1411,6 +1414,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (A.has_idm) {
                 sig[i] = 0.f;
                 agent[i] = A.idmA[o0 + i];
+                if (agent[i]) {   // the pose at progress 0 and its segment
+                    const float4 *path = A.idmP + (long)(o0 + i) * (A.T + 1);
+                    const int lo = idm_segment([&](int k) { return path[k].w; }, A.T, 0.f);
+                    float x, y, yaw;
+                    idm_interp(path, A.T, lo, 0.f, x, y, yaw);
+                    sg[i] = lo;
+                    pc[2 * i] = x;
+                    pc[2 * i + 1] = y;
+                }
             }
         }
         if (A.has_ckpt)
@@ -1450,7 +1462,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const float pvx = L.vx[i], pvy = L.vy[i], pyaw = L.yaw[i];
                 const bool pvalid = L.valid[i];
                 if (!L.ctrl[i] && A.has_idm && agent[i]) {
-                    idm_move(A, L, i, g, row, sig, ia[i]);
+                    idm_move(A, L, i, g, row, sig, sg, pc, ia[i]);
                 } else if (!L.ctrl[i]) {
                     load_object(L, i, A.log, row + g);
                 } else if (L.valid[i]) {
@@ -1716,7 +1728,7 @@ void launch_offroad(const wm_batch &b, const OffroadArgs &a, hipStream_t st)
 size_t rollout_lds_bytes(int maxN, int G, int CW)
 {
     const int nthr = 64 * CW * G;
-    const size_t idm = (size_t)maxN * 12 + align_up((size_t)maxN, 16) + (size_t)maxN * 8 +
+    const size_t idm = (size_t)maxN * 12 + align_up((size_t)maxN, 16) + (size_t)maxN * 12 +
                        (maxN <= kIdmMaskMaxN ? (size_t)maxN * ((maxN + 31) / 32) * 4 : 0);
     // boxes, previous nearest points, keys, order, group counter; the packed
     // boxes of the overlap
