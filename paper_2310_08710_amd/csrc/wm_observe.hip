@@ -1181,19 +1181,28 @@ void launch_observe(const wm_batch &b, const ObserveArgs &a, int rows, hipStream
     // order (each row's bound then comes from the previous one), so a
     // work-group takes as many observations as leave about four work-groups
     // per resident slot: consecutive rows of one ego, or, with fewer rows
-    // than that, all rows of several egos.
+    // than that, all rows of several egos.  Calls of fewer than
+    // kBlockMinRows rows bound the blocks for too few observations: they
+    // take the block form only when there are at least two observations per
+    // resident slot (one work-group per slot, each bounding once for several
+    // egos), the form with one work-group per observation otherwise.
     const long S = b.num_scenarios;
     const long items = (long)rows * S * a.E;
-    if (rows < kBlockMinRows) {
+    const long slots = items >= 2 ? observe_slots() : 1;
+    if (rows < kBlockMinRows && items < 2 * slots) {
         hipLaunchKernelGGL(k_observe_each, dim3((unsigned)items), dim3(kObsThreads), 0, st, a, rows);
         return;
     }
-    const long slots = observe_slots();
-    long per = items / (4 * slots);
+    long per = rows < kBlockMinRows ? items / slots : items / (4 * slots);
     if (per < 1)
         per = 1;
     int row_chunk = rows, ego_chunk = 1;
-    if (rows >= per) {
+    if (rows < kBlockMinRows) {
+        const long ec = per / rows;
+        ego_chunk = (int)(ec < a.E ? ec : a.E);
+        if (ego_chunk < 1)
+            ego_chunk = 1;
+    } else if (rows >= per) {
         row_chunk = (int)per;
     } else {
         const long ec = per / rows;
