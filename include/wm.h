@@ -135,10 +135,13 @@ typedef struct wm_metrics {
 /* Optional launch tuning of the off-road / rollout kernels; NULL selects the
  * library's choice (autotuned table if wm_autotune has run, else a default).
  *   unit_objects  objects per work unit (one work-group): 64, 128 or 256
- *   edge_splits   1, 2, 4, 8 or 16: for wm_offroad, the road-edge ranges
- *                 scanned in parallel per object; for the rollouts, the
- *                 work-group's waves per 64 objects, which claim the unit's
- *                 groups of four objects for the off-road scan
+ *   edge_splits   1, 2, 4, 8 or 16: the work-group's waves per 64
+ *                 objects.  In the rollouts, and in wm_offroad / wm_step
+ *                 with a work-group of at most 512 threads, they claim the
+ *                 unit's groups of four objects for the pruned off-road
+ *                 scan; in wm_offroad with a larger work-group (the scan of
+ *                 every point), they scan that many road-edge ranges of
+ *                 each object in parallel
  * unit_objects * edge_splits (the work-group size) must not exceed 1024 for
  * wm_offroad and 512 for wm_rollout / wm_autotune; larger values fail with
  * WM_ERR_RANGE. */
