@@ -834,7 +834,8 @@ __device__ void offroad_unit_pruned(const ObjLds &L, int i0, int Ns, const float
 // A real road-edge point near (x, y), for a pruned scan with no nearest
 // point of a previous step: the block whose box has the nearest farthest
 // corner (among the chunks whose boxes may hold a point nearer than the best
-// chunk's farthest corner), and in it the nearest point of index < E.  Any
+// chunk's farthest corner; earlier blocks win ties), and in it the nearest
+// point of index < E.  Any
 // real point bounds the corner's nearest distance (scan_group_pruned); this
 // one is close to it.  (+inf, +inf) without edges.
 __device__ float2 seed_point(const float *__restrict__ stream, const float4 *cbox, const float4 *box, int E, float x,
@@ -846,32 +847,67 @@ __device__ float2 seed_point(const float *__restrict__ stream, const float4 *cbo
         const float fy = fabsf(b.z - y) > fabsf(b.w - y) ? b.z : b.w;
         return edge_d2(fx, fy, x, y);
     };
-    float fc = __builtin_inff();
-    for (int c = 0; c < nch; ++c)
-        fc = fminf(fc, far_d2(cbox[c]));
-    float fb = __builtin_inff();
+    // One pass over the chunks, four at a time (their box reads in flight
+    // together): fc is the nearest farthest chunk corner so far, and the
+    // blocks of every chunk whose box may hold a point nearer than fc are
+    // tested.  A chunk tested only because fc was still larger never wins:
+    // its blocks' farthest corners lie beyond its nearest point, beyond the
+    // final fc, and the best block of the chunk attaining the final fc lies
+    // within it.
+    float fc = __builtin_inff(), fb = __builtin_inff();
     int bb = -1;
-    for (int c = 0; c < nch; ++c)
-        if (box_lb(cbox[c], x, y) <= fc)
-            for (int j = 0; j < 4; ++j) {
-                const float d = far_d2(box[4 * c + j]);
-                if (d < fb) {
-                    fb = d;
-                    bb = 4 * c + j;
+    for (int c0 = 0; c0 < nch; c0 += 4) {
+        float4 b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            b[k] = cbox[min(c0 + k, nch - 1)];   // past the end: the last box again
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            fc = fminf(fc, far_d2(b[k]));
+            if (c0 + k < nch && box_lb(b[k], x, y) <= fc) {
+                const int c = c0 + k;
+                float4 bx[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    bx[jj] = box[4 * c + jj];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const float d = far_d2(bx[jj]);
+                    if (d < fb) {
+                        fb = d;
+                        bb = 4 * c + jj;
+                    }
                 }
             }
+        }
+    }
     float2 q = make_float2(__builtin_inff(), __builtin_inff());
     if (bb < 0)
         return q;
+    // the block's points in ascending order, 16 at a time (four 16-byte
+    // loads of x and of y in flight; the chunk's storage covers all 32)
     const float *col = stream + kChunkFloats * (bb >> 2) + 32 * (bb & 3);
     const int n = min(32, E - 32 * bb);
     float best = __builtin_inff();
-    for (int j = 0; j < n; ++j) {
-        const float px = col[j], py = col[kChunk + j];
-        const float d = edge_d2(px, py, x, y);
-        if (d < best) {
-            best = d;
-            q = make_float2(px, py);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float4 X[4], Y[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            X[v] = ((const float4 *)col)[4 * h + v];
+            Y[v] = ((const float4 *)(col + kChunk))[4 * h + v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float xs[4] = {X[v].x, X[v].y, X[v].z, X[v].w}, ys[4] = {Y[v].x, Y[v].y, Y[v].z, Y[v].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float d = edge_d2(xs[k], ys[k], x, y);
+                if (16 * h + 4 * v + k < n && d < best) {
+                    best = d;
+                    q = make_float2(xs[k], ys[k]);
+                }
+            }
         }
     }
     return q;
